@@ -1,0 +1,342 @@
+#!/usr/bin/env python3
+"""Benchmark of the 14-addition approximate-DCT block codec on one MI355X.
+
+A step is one pass of the whole hot path over the batch of 64 uint8 images of
+4096 x 4096 (per-image Q_ij = 1 + s (i + j)): one persistent launch of the
+fused forward + quantise kernel over all 64 images, then one persistent launch
+of the fused dequantise + inverse kernel (int16 coefficients in between).
+`value` is pixels per second of that step (Gpixel/s, encode + decode), with
+inputs resident in HBM before the timed region starts.
+
+The JSON line also carries:
+  roofline      the dominant kernel's algorithmic HBM bytes (3 B/px: 1 in,
+                2 out for the encoder; 2 in, 1 out for the decoder) per launch
+                over its average launch time, measured with HIP events on the
+                launch stream, against the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle (dense 8x8 integer products) encoding and
+                decoding a bounded sample of the same images on the host cores;
+  batched       10,000 ragged images as one persistent launch replayed from a
+                hipGraph vs one plain launch per image (--no-extras skips);
+  serving       Poisson request streams served with continuous batching vs a
+                plain launch per request: p50/p99 latency and Gpixel/s.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("tdct_kernels.hip", "tdct_device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1702_00817_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name: str):
+    """HBM traffic per launch from a committed rocprofv3 counter summary,
+    or None when absent or taken from a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_source") != kernel_source_hash():
+        return None
+    return d
+
+
+def make_large_batch(tdct, torch, n, side):
+    import synth
+    sizes, seeds, qs = synth.large_batch_spec(n=n, side=side)
+    t0 = time.time()
+    buf, off, strides = synth.batch(sizes, seeds)
+    log("generated %d x %d^2 images in %.1fs" % (n, side, time.time() - t0))
+    src = torch.from_numpy(buf).cuda()
+    nblk = (side // 8) ** 2
+    coef = torch.empty((n, nblk, 64), dtype=torch.int16, device="cuda")
+    dst = torch.empty((n, side, side), dtype=torch.uint8, device="cuda")
+    base = src.data_ptr()
+    enc = [tdct.image_desc(tdct.OP_ENCODE, side, side, qtab=i, keep=64, src=base + int(off[i]),
+                           src_stride=side, coef=coef[i]) for i in range(n)]
+    dec = [tdct.image_desc(tdct.OP_DECODE, side, side, qtab=i, coef=coef[i], dst=dst[i],
+                           dst_stride=side) for i in range(n)]
+    return dict(buf=buf, off=off, strides=strides, sizes=sizes, qs=qs, src=src, coef=coef, dst=dst,
+                enc=enc, dec=dec, pixels=n * side * side)
+
+
+def time_steps(tdct, torch, pe, pd, steps, warmup, stream):
+    for _ in range(warmup):
+        tdct.tdct_batch_run(pe, stream)
+        tdct.tdct_batch_run(pd, stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        tdct.tdct_batch_run(pe, stream)
+        ev[k][1].record(stream)
+        tdct.tdct_batch_run(pd, stream)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    enc_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    dec_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+    return wall, enc_ms, dec_ms
+
+
+def cpu_baseline(W, budget_s=15.0):
+    """The oracle, as it stands, on the host cores: encode + decode of whole
+    4096 x 4096 images from the same batch, one after another, until the
+    time budget is spent (at least one image)."""
+    import numpy as np
+
+    import oracle as O
+    import synth
+    threads = max(1, min(os.cpu_count() or 1, 64))
+    px = 0
+    done = 0
+    t0 = time.perf_counter()
+    for i in range(len(W["sizes"])):
+        img = synth.batch_view(W["buf"], W["off"], W["strides"], W["sizes"], i)
+        w, h = W["sizes"][i]
+        q = O.quantise(img, W["qs"][i], 64, threads=threads)
+        O.inverse(q, W["qs"][i], w, h, threads=threads)
+        px += w * h
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    del np
+    return {"value": round(px / dt / 1e9, 4), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
+            "sample": "encode+decode of %d of the %d 4096x4096 images (%.1f s wall), dense 8x8 "
+                      "integer products, %d threads, %s" % (done, len(W["sizes"]), dt, threads, cpu_model)}
+
+
+def batched_leg(tdct, torch, stream, n=10000, reps=5):
+    """10,000 ragged images, encode + decode round trip with coefficients:
+    persistent launch (graph replay) vs one plain launch per image."""
+    import numpy as np
+
+    import synth
+    sizes, seeds, qs = synth.ragged_batch_spec(n=n)
+    t0 = time.time()
+    buf, off, strides = synth.batch(sizes, seeds)
+    log("generated %d ragged images (%.2f Gpx) in %.1fs" % (n, buf.size / 1e9, time.time() - t0))
+    src = torch.from_numpy(buf).cuda()
+    nblk = np.array([(w // 8) * (h // 8) for w, h in sizes], np.int64)
+    boff = np.concatenate([[0], np.cumsum(nblk)])
+    coef = torch.empty((int(boff[-1]), 64), dtype=torch.int16, device="cuda")
+    dst = torch.empty(buf.size, dtype=torch.uint8, device="cuda")
+    base, cb, db = src.data_ptr(), coef.data_ptr(), dst.data_ptr()
+    descs = [tdct.image_desc(tdct.OP_ROUNDTRIP, w, h, qtab=i, keep=64, src=base + int(off[i]),
+                             src_stride=w, coef=cb + 128 * int(boff[i]), dst=db + int(off[i]),
+                             dst_stride=w) for i, (w, h) in enumerate(sizes)]
+    px = int(sum(w * h for w, h in sizes))
+    plan = tdct.tdct_batch_plan(descs, qs)
+    try:
+        tune = tdct.tdct_autotune(plan, stream, reps=2)
+        tdct.tdct_batch_graph(plan, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tdct.tdct_batch_graph(plan, stream)
+        torch.cuda.synchronize()
+        graph_s = (time.perf_counter() - t0) / reps
+        tdct.tdct_run_per_image(descs, qs, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tdct.tdct_run_per_image(descs, qs, stream)
+        torch.cuda.synchronize()
+        per_s = (time.perf_counter() - t0) / reps
+        info = tdct.tdct_plan_info_get(plan)
+    finally:
+        tdct.tdct_plan_free(plan)
+    del src, coef, dst
+    return {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
+            "graph_gpx_s": round(px / graph_s / 1e9, 2), "graph_ms": round(graph_s * 1e3, 3),
+            "per_image_gpx_s": round(px / per_s / 1e9, 2), "per_image_ms": round(per_s * 1e3, 3),
+            "speedup": round(per_s / graph_s, 2), "bytes_per_px": 6}
+
+
+def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
+    """Poisson encode/decode requests with device-resident payloads, served by
+    continuous batching and by one plain launch per request."""
+    import numpy as np
+
+    import synth
+    max_side = 8192
+    pool_n = 4
+    log("serving: building a payload pool of %d planes of %d^2" % (pool_n, max_side))
+    pool = [torch.from_numpy(synth.plane(max_side, max_side, 5000 + k)).cuda() for k in range(pool_n)]
+    # decode inputs: encoder output of the pool planes (any int16 is a valid input)
+    nblk = (max_side // 8) ** 2
+    coefs = []
+    for k in range(pool_n):
+        c = torch.empty((nblk, 64), dtype=torch.int16, device="cuda")
+        tdct.tdct_quantise(pool[k], max_side, max_side, max_side, synth.qtable(1, 1 + k), 64, c)
+        coefs.append(c)
+    torch.cuda.synchronize()
+    out = {}
+    for rate in rates:
+        tr = synth.serving_trace(rate, seconds, seed=5)
+        reqs = []
+        for k in range(len(tr["t"])):
+            w, h, s = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k])
+            p = k % pool_n
+            if tr["op"][k] == 0:
+                reqs.append(tdct.request(tdct.OP_ENCODE, w, h, pool[p], synth.qtable(1, s), keep=64,
+                                         in_stride=max_side))
+            else:
+                reqs.append(tdct.request(tdct.OP_DECODE, w, h, coefs[p], synth.qtable(1, s)))
+        arrival = (tr["t"] * 1e6).tolist()
+        px = int((tr["w"] * tr["h"]).sum())
+        res = {"requests": len(reqs), "mpx_mean": round(px / max(1, len(reqs)) / 1e6, 3)}
+        for mode, batching in (("batched", 1), ("per_request", 0)):
+            srv = tdct.tdct_server_create(tdct.server_cfg(64 << 30, streams=streams, max_batch=64,
+                                                          max_wait_us=0, batching=batching))
+            try:
+                t0 = time.perf_counter()
+                _, lat, st = tdct.tdct_server_replay(srv, reqs, arrival)
+                wall = time.perf_counter() - t0
+                stats = tdct.tdct_server_stats(srv)
+            finally:
+                tdct.tdct_server_destroy(srv)
+            lat = np.array([x for x, s_ in zip(lat, st) if s_ == 0])
+            res[mode] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                         "p99_us": round(float(np.percentile(lat, 99)), 1),
+                         "p999_us": round(float(np.percentile(lat, 99.9)), 1),
+                         "failed": int(sum(1 for s_ in st if s_ != 0)),
+                         "delivered_gpx_s": round(px / wall / 1e9, 3),
+                         "busy_gpx_s": round(px / max(stats["busy_us"], 1.0) / 1e3, 2),
+                         "batches": stats["batches"], "mean_batch": round(stats["mean_batch"], 2),
+                         "arena_high_water_gb": round(stats["arena_high_water"] / 1e9, 3)}
+        out[str(rate)] = res
+        log("serving %d req/s: %s" % (rate, json.dumps(res)))
+    return {"seconds_per_rate": seconds, "streams": streams, "budget_gb": 64, "rates": out}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--images", type=int, default=64)
+    ap.add_argument("--side", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
+    ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
+    ap.add_argument("--serving-seconds", type=float, default=4.0)
+    ap.add_argument("--copy-only", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; the codec shards by image with no "
+              "cross-GPU exchange (see the design notes), so --gpus %d is not run." % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1702_00817_amd as tdct
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+
+    if args.copy_only:
+        n = args.copy_only << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 5}))
+        return
+
+    W = make_large_batch(tdct, torch, args.images, args.side)
+    pe = tdct.tdct_batch_plan(W["enc"], W["qs"])
+    pd = tdct.tdct_batch_plan(W["dec"], W["qs"])
+    try:
+        tune_e = tune_d = None
+        if not args.no_tune:
+            tune_e = tdct.tdct_autotune(pe, stream, reps=3)
+            tune_d = tdct.tdct_autotune(pd, stream, reps=3)
+            log("autotune: encode %s decode %s" % (tune_e, tune_d))
+        wall, enc_ms, dec_ms = time_steps(tdct, torch, pe, pd, args.steps, args.warmup, stream)
+    finally:
+        tdct.tdct_plan_free(pe)
+        tdct.tdct_plan_free(pd)
+    px = W["pixels"]
+    ms_step = wall / args.steps * 1e3
+    enc_avg, dec_avg = sum(enc_ms) / len(enc_ms), sum(dec_ms) / len(dec_ms)
+    dom_name, dom_ms = ("encode", enc_avg) if enc_avg >= dec_avg else ("decode", dec_avg)
+    bytes_launch = 3 * px
+    achieved = bytes_launch / (dom_ms / 1e3) / 1e9
+    traffic = load_traffic(dom_name + "_64x4096")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
+            "kernel": "batch_kernel (%s), 64 x 4096^2, %d B/px algorithmic" % (dom_name, 3),
+            "encode_ms": round(enc_avg, 4), "decode_ms": round(dec_avg, 4),
+            "encode_gbs": round(bytes_launch / (enc_avg / 1e3) / 1e9, 1),
+            "decode_gbs": round(bytes_launch / (dec_avg / 1e3) / 1e9, 1)}
+    result = {
+        "metric": "Gpixel/s encode+decode (64 x 4096x4096 uint8, fused kernels), % HBM peak",
+        "value": round(px / (ms_step / 1e3) / 1e9, 2),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic (seeded blob fields + noise)",
+        "config": {"workload": "64 x 4096x4096 uint8 images, per-image Q_ij = 1 + s(i+j), "
+                               "encode (int16 out) + decode (uint8 out)",
+                   "images": args.images, "side": args.side, "pixels": px,
+                   "tune": {"encode": tune_e, "decode": tune_d}},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)...")
+        result["cpu_baseline"] = cpu_baseline(W)
+    del W
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("batched leg...")
+        result["batched"] = batched_leg(tdct, torch, stream)
+        torch.cuda.empty_cache()
+        log("serving leg...")
+        result["serving"] = serving_leg(tdct, torch, args.serving_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,259 @@
+/*
+ * tdct: an MI355X (gfx950) block codec built on the 8-point approximate DCT
+ * of Bayer and Cintra, "DCT-like Transform for Image Compression Requires 14
+ * Additions Only".
+ *
+ * The transform (Section 2) is the 8x8 matrix T with entries in {0, +1, -1};
+ * its fast algorithm needs 14 additions, no multiplications and no shifts
+ * (Section 2, Table 1). Images are split into 8x8 blocks that are transformed
+ * along rows and columns (Section 3). This library runs that 2-D transform as
+ * an integer codec on row-major uint8 planes:
+ *
+ *   encode  X = block - 128, Y = T X T^t,
+ *           W_ij = Y_ij * 2^(6 - a_i - a_j)      (a = 3,1,2,1,3,1,2,1: the
+ *                                                 diagonal D of Section 2
+ *                                                 enters only as D^2, merged
+ *                                                 into quantisation),
+ *           q_ij = round-half-away(W_ij / Q_ij),
+ *           q_ij = 0 where the zigzag rank of (i, j) is >= keep (zonal
+ *           coding of Section 3);
+ *   decode  W'_ij = q_ij Q_ij,  S = T^t W' T,
+ *           pixel = clamp(floor((S + 32) / 64) + 128, 0, 255)
+ *           (the inverse transform of Section 3 with the scale 64 removed).
+ *
+ * Everything is integer and exact: one correct output exists for any input.
+ *
+ * Conventions for every entry point:
+ *  - Data pointers are DEVICE pointers owned by the caller; the plain calls
+ *    allocate nothing.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *    stream) and return once the work is enqueued.
+ *  - Errors are returned as tdct_status codes; no exception crosses the ABI.
+ *    TDCT_EDEVICE means a HIP runtime call failed; tdct_last_error() then
+ *    returns its text for the calling thread.
+ *  - Planes: w and h are positive multiples of 8 (TDCT_EDIM otherwise),
+ *    at most 65536 each, the row stride in bytes is >= w. Any pixel pointer
+ *    and stride are accepted; 8- and 16-byte aligned ones take faster loads.
+ *  - Coefficients: block b = by * (w / 8) + bx (raster order) holds its 64
+ *    coefficients contiguously at [b * 64 + 8 i + j], i = vertical and
+ *    j = horizontal frequency (int16 or int32), or at [b * 64 + rank] in
+ *    zigzag order (int8). Coefficient pointers must be 16-byte aligned
+ *    (TDCT_EINVAL otherwise).
+ *  - Quantisation tables hold Q_ij in natural (i, j) order, each in
+ *    [1, 4095] (TDCT_EQTAB otherwise); this range keeps every intermediate of
+ *    the decoder inside int32 for any int16 input.
+ *  - Plain calls are reentrant; plans and servers are used from one thread
+ *    at a time unless stated.
+ */
+#ifndef TDCT_H
+#define TDCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TDCT_OK = 0,
+    TDCT_EINVAL = -1,    /* null pointer, stride < w, misaligned coefficients, bad keep/op */
+    TDCT_EDIM = -2,      /* w or h not a positive multiple of 8, or above 65536 */
+    TDCT_EQTAB = -3,     /* a Q entry outside [1, 4095] */
+    TDCT_ENOMEM = -4,    /* device allocation failed, or a request larger than the budget */
+    TDCT_EDEVICE = -5,   /* a HIP runtime call failed (see tdct_last_error) */
+    TDCT_EBUSY = -6,     /* result not ready yet, or the server is shutting down */
+    TDCT_ENOTFOUND = -7  /* unknown or already released ticket */
+} tdct_status;
+
+#define TDCT_QMAX 4095
+#define TDCT_MAX_SIDE 65536
+
+typedef struct {
+    uint16_t q[64]; /* Q_ij at [8 i + j] */
+} tdct_qtable;
+
+/* ---- plain calls: one image ------------------------------------------ */
+
+/* Forward transform only (Section 3's 2-D block transform of T, Section 2):
+ * coef[b*64 + 8i + j] = Y_ij = (T (X - 128) T^t)_ij, int32, unscaled. */
+int tdct_forward(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h, int32_t* coef,
+                 void* stream);
+
+/* Fused forward + quantise (encode): q[b*64 + 8i + j] = q_ij as defined
+ * above, with zonal retention of the first `keep` zigzag coefficients
+ * (1..64; 64 keeps all). */
+int tdct_quantise(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
+                  const tdct_qtable* Q, int32_t keep, int16_t* q, void* stream);
+
+/* Fused dequantise + inverse (decode) of any int16 coefficients into a
+ * uint8 plane (dst rows of w bytes at dst_stride). */
+int tdct_inverse(const int16_t* q, const tdct_qtable* Q, int32_t w, int32_t h, uint8_t* dst,
+                 int64_t dst_stride, void* stream);
+
+/* Encode then decode in one pass: dst = decode(encode(src)). The
+ * coefficients are also written to q_or_null unless it is NULL (then they
+ * never leave the registers). src and dst may be the same plane. */
+int tdct_roundtrip(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
+                   const tdct_qtable* Q, int32_t keep, int16_t* q_or_null, uint8_t* dst,
+                   int64_t dst_stride, void* stream);
+
+/* Encode with int8 saturation (clamp to [-128, 127] after rounding), stored
+ * in zigzag order: out[b*64 + rank] (64 bytes per block, no zonal mask). */
+int tdct_quantise_i8_zigzag(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
+                            const tdct_qtable* Q, int8_t* out, void* stream);
+
+/* Sum of squared differences of two uint8 planes (for PSNR / MSE, the
+ * figures of merit of Section 3), exact, written to *sse_dev (a device
+ * uint64). */
+int tdct_sse(const uint8_t* a, int64_t a_stride, const uint8_t* b, int64_t b_stride, int32_t w,
+             int32_t h, uint64_t* sse_dev, void* stream);
+
+const char* tdct_strerror(int status);
+const char* tdct_last_error(void);
+
+/* ---- batch form: many images of uneven sizes in one persistent launch -- */
+
+enum {
+    TDCT_OP_ENCODE = 0,      /* src -> int16 coef */
+    TDCT_OP_DECODE = 1,      /* int16 coef -> dst */
+    TDCT_OP_ROUNDTRIP = 2,   /* src -> dst, int16 coef too if coef != NULL */
+    TDCT_OP_ENCODE_I8ZZ = 3, /* src -> int8 zigzag coef */
+    TDCT_OP_FORWARD = 4      /* src -> int32 Y */
+};
+
+typedef struct {
+    int32_t op;   /* TDCT_OP_* */
+    int32_t w, h; /* positive multiples of 8 */
+    int32_t qtab; /* index into the plan's Q tables (ignored by FORWARD) */
+    int32_t keep; /* 1..64 (ENCODE, ROUNDTRIP); ignored otherwise */
+    int32_t reserved;
+    const uint8_t* src;
+    int64_t src_stride;
+    void* coef; /* device, 16-byte aligned; element type per op */
+    uint8_t* dst;
+    int64_t dst_stride;
+} tdct_image_desc;
+
+/* Launch shape of the persistent kernel. Zero fields take defaults. */
+typedef struct {
+    int32_t waves_per_group; /* 1, 2, 4, 8 or 16 (64-lane waves per workgroup) */
+    int32_t groups_per_cu;   /* resident workgroups per compute unit; grid = CUs * this */
+    int32_t tile_waves;      /* consecutive wave-tiles one wave takes per step (1, 2, 4) */
+    int32_t reserved;
+} tdct_tune;
+
+typedef struct {
+    int64_t images;
+    int64_t blocks;
+    int64_t tiles;
+    int64_t pixels;
+    int64_t table_bytes; /* device bytes held by the plan's tables */
+    tdct_tune tune;      /* launch shape in use */
+} tdct_plan_info;
+
+typedef struct tdct_plan tdct_plan;
+
+/* Build a plan: validates every image, computes the int64 prefix sum of
+ * blocks per image and the image-uniform tile list, and uploads both with
+ * the per-table quantiser constants to device tables the plan owns.
+ * Image descriptors and tables are copied; device buffers they name must
+ * stay valid while the plan is run. */
+int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
+                    int32_t nq, const tdct_tune* tune_or_null, tdct_plan** out);
+
+/* One persistent launch over every tile of the plan on `stream`. */
+int tdct_batch_run(tdct_plan* plan, void* stream);
+
+/* Same work as tdct_batch_run, through a hipGraph captured on the first
+ * call (on `stream`) and replayed afterwards. */
+int tdct_batch_graph(tdct_plan* plan, void* stream);
+
+/* Times candidate launch shapes on the plan (reps launches each, after one
+ * warm-up), keeps the fastest in the plan and returns it in *best. Outputs
+ * are overwritten with the same bytes by every candidate. */
+int tdct_autotune(tdct_plan* plan, void* stream, int32_t reps, tdct_tune* best);
+
+int tdct_plan_info_get(const tdct_plan* plan, tdct_plan_info* out);
+void tdct_plan_free(tdct_plan* plan);
+
+/* Per-image launches of the same work (one plain call per image in order,
+ * on `stream`), the baseline the batch form is compared with. */
+int tdct_run_per_image(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
+                       int32_t nq, void* stream);
+
+/* ---- serving form ------------------------------------------------------ */
+
+typedef struct {
+    int64_t budget_bytes;  /* device arena for request outputs (admission limit) */
+    int32_t streams;       /* batches that may be in flight at once (1..16) */
+    int32_t max_batch;     /* requests per batch, at most */
+    int32_t max_wait_us;   /* a batch launches when a stream is free and either the
+                              queue holds max_batch requests or the oldest waited this long */
+    int32_t batching;      /* 1 = continuous batching into the persistent kernel;
+                              0 = one plain launch per request (comparison mode) */
+    tdct_tune tune;        /* launch shape of batch launches (zeros = defaults) */
+    int32_t fake_device_us; /* > 0: no GPU at all -- outputs live in host memory and a
+                               batch "completes" this many microseconds after launch
+                               (exercises admission and batching on a CPU) */
+    int32_t fake_fail_every; /* fake device only: every n-th batch fails (0 = never) */
+} tdct_server_cfg;
+
+typedef struct {
+    int32_t op;      /* TDCT_OP_ENCODE or TDCT_OP_DECODE */
+    int32_t w, h;
+    int32_t keep;    /* ENCODE only */
+    const void* input; /* device: uint8 plane (ENCODE) or int16 coefficients (DECODE) */
+    int64_t in_stride; /* ENCODE: bytes per row */
+    tdct_qtable Q;
+} tdct_request;
+
+typedef struct {
+    int32_t status;       /* TDCT_OK done, TDCT_EBUSY pending, < 0 failed */
+    int32_t batch_size;   /* requests in the launch that served it */
+    void* output;         /* device, in the arena: int16 [w*h/64][64] or uint8 [h][w] */
+    int64_t output_bytes;
+    double submit_us;     /* host clock, microseconds since server start */
+    double done_us;       /* completion observed on the host */
+} tdct_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected;
+    int64_t batches;
+    int64_t pixels_done;
+    int64_t arena_bytes_in_use, arena_high_water;
+    double busy_us;       /* wall time with at least one batch in flight */
+    double p50_us, p99_us, p999_us, mean_us; /* latency, submit -> completion observed */
+    double mean_batch;
+} tdct_stats;
+
+typedef struct tdct_server tdct_server;
+
+int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out);
+/* Queues a request (never blocks on the GPU). TDCT_ENOMEM if its output
+ * alone exceeds the budget; otherwise it waits for arena space in FIFO
+ * order. */
+int tdct_server_submit(tdct_server* s, const tdct_request* req, uint64_t* ticket);
+/* Non-blocking status; TDCT_ENOTFOUND for unknown tickets. */
+int tdct_server_poll(tdct_server* s, uint64_t ticket, tdct_result* out);
+/* Blocks until the request completes (or fails). */
+int tdct_server_wait(tdct_server* s, uint64_t ticket, tdct_result* out);
+/* Returns the request's output memory to the arena; the ticket is gone. */
+int tdct_server_release(tdct_server* s, uint64_t ticket);
+/* Blocks until every submitted request has completed. */
+int tdct_server_drain(tdct_server* s);
+int tdct_server_stats(tdct_server* s, tdct_stats* out);
+void tdct_server_destroy(tdct_server* s);
+
+/* Open-loop replay: request k is submitted at arrival_us[k] after the call
+ * starts (host clock); outputs are released as they complete unless
+ * keep_outputs. latency_us[k] receives submit -> completion; status[k] the
+ * final status. Returns after every request has completed. */
+int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us,
+                       int32_t n, int32_t keep_outputs, uint64_t* tickets_out,
+                       double* latency_us, int32_t* status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDCT_H */

@@ -59,6 +59,7 @@ def lib():
             L.oracle_get_zigzag.argtypes = [P]
             L.oracle_round_div.argtypes = [i64, i64]
             L.oracle_round_div.restype = i64
+            L.oracle_round_div_array.argtypes = [P, i64, i64, P]
             L.oracle_apply_T.argtypes = [P, P, i32]
             L.oracle_forward_block.argtypes = [P, P]
             L.oracle_inverse_block.argtypes = [P, P]
@@ -105,6 +106,13 @@ def zigzag_rank() -> np.ndarray:
 
 def round_div(W: int, Q: int) -> int:
     return int(lib().oracle_round_div(int(W), int(Q)))
+
+
+def round_div_array(W, Q: int) -> np.ndarray:
+    Wa = np.ascontiguousarray(np.asarray(W, np.int64).reshape(-1))
+    out = np.zeros_like(Wa)
+    lib().oracle_round_div_array(_ptr(Wa), Wa.size, int(Q), _ptr(out))
+    return out
 
 
 def apply_T(x, transpose: bool = False) -> np.ndarray:

@@ -121,6 +121,11 @@ int64_t oracle_round_div(int64_t W, int64_t Q) {
     return W < 0 ? -m : m;
 }
 
+/* out[k] = round-half-away(W[k] / Q) for k < n. */
+void oracle_round_div_array(const int64_t* W, int64_t n, int64_t Q, int64_t* out) {
+    for (int64_t k = 0; k < n; ++k) out[k] = oracle_round_div(W[k], Q);
+}
+
 /* 1-D: y = T * x (transpose = 0) or y = T^t * x (transpose = 1). */
 void oracle_apply_T(const int64_t x[8], int64_t y[8], int32_t transpose) {
     for (int k = 0; k < 8; ++k) {

@@ -1,0 +1,365 @@
+// Batch form: many images of uneven sizes in one persistent launch.
+//
+// Planning (host): the int64 prefix sum of blocks per image gives every
+// image its global block range; each image is cut into wave-tiles (128
+// blocks for encoder-side ops, 64 for the decoder) that never straddle two
+// images, so everything a wave needs besides pixels -- the image descriptor
+// and the quantiser constants -- is uniform across the wave and comes from
+// scalar loads. The tables (tiles, descriptors, constants) live in one device
+// allocation the plan owns. A run is one launch of the persistent kernel;
+// the graph variant captures that launch once and replays it.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "tdct.h"
+#include "tdct_internal.hpp"
+
+using namespace tdct;
+
+struct tdct_plan {
+    std::vector<ImgDesc> imgs;
+    std::vector<QConst> qcs;
+    std::vector<Tile> tiles;
+    std::vector<int64_t> blk_off;  // prefix sum of blocks, n + 1 entries
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    Tile* tiles_d = nullptr;
+    ImgDesc* imgs_d = nullptr;
+    QConst* qcs_d = nullptr;
+    tdct_tune tune{};
+    int num_cus = 0;
+    int64_t pixels = 0;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+tdct_tune default_tune() {
+    tdct_tune t{};
+    t.waves_per_group = 4;
+    t.groups_per_cu = 8;
+    t.tile_waves = 1;
+    return t;
+}
+
+int normalise_tune(const tdct_tune* in, tdct_tune* out) {
+    tdct_tune t = default_tune();
+    if (in) {
+        if (in->waves_per_group) t.waves_per_group = in->waves_per_group;
+        if (in->groups_per_cu) t.groups_per_cu = in->groups_per_cu;
+        if (in->tile_waves) t.tile_waves = in->tile_waves;
+    }
+    const int w = t.waves_per_group;
+    if (!(w == 1 || w == 2 || w == 4 || w == 8 || w == 16)) return TDCT_EINVAL;
+    if (t.groups_per_cu < 1 || t.groups_per_cu > 64) return TDCT_EINVAL;
+    if (!(t.tile_waves == 1 || t.tile_waves == 2 || t.tile_waves == 4)) return TDCT_EINVAL;
+    *out = t;
+    return TDCT_OK;
+}
+
+int validate_image(const tdct_image_desc& im, int32_t nq) {
+    switch (im.op) {
+        case TDCT_OP_ENCODE:
+        case TDCT_OP_ROUNDTRIP:
+            if (im.keep < 1 || im.keep > 64) return TDCT_EINVAL;
+            break;
+        case TDCT_OP_DECODE:
+        case TDCT_OP_ENCODE_I8ZZ:
+        case TDCT_OP_FORWARD:
+            break;
+        default:
+            return TDCT_EINVAL;
+    }
+    if (im.op != TDCT_OP_FORWARD && (im.qtab < 0 || im.qtab >= nq)) return TDCT_EINVAL;
+    int st;
+    if (im.op != TDCT_OP_DECODE) {
+        if ((st = validate_plane(im.src, im.src_stride, im.w, im.h))) return st;
+    }
+    if (im.op == TDCT_OP_DECODE || im.op == TDCT_OP_ROUNDTRIP) {
+        if ((st = validate_plane(im.dst, im.dst_stride, im.w, im.h))) return st;
+    } else if (im.w <= 0 || im.h <= 0 || (im.w & 7) || (im.h & 7)) {
+        return TDCT_EDIM;
+    }
+    const bool need_coef = im.op != TDCT_OP_ROUNDTRIP;
+    if (need_coef && !im.coef) return TDCT_EINVAL;
+    if (im.coef && ((uintptr_t)im.coef % 16)) return TDCT_EINVAL;
+    return TDCT_OK;
+}
+
+void free_graph(tdct_plan* p) {
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+int run(tdct_plan* p, hipStream_t s) {
+    return launch_batch(p->tiles_d, p->imgs_d, p->qcs_d, (uint32_t)p->tiles.size(), p->tune,
+                        p->num_cus, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs, int32_t nq,
+                    const tdct_tune* tune_or_null, tdct_plan** out) {
+    if (!out || n < 0 || (n > 0 && !imgs) || nq < 0 || (nq > 0 && !qtabs)) return TDCT_EINVAL;
+    *out = nullptr;
+    tdct_tune tune;
+    int st = normalise_tune(tune_or_null, &tune);
+    if (st) return st;
+    for (int32_t k = 0; k < nq; ++k)
+        if ((st = validate_q(&qtabs[k]))) return st;
+    for (int32_t i = 0; i < n; ++i)
+        if ((st = validate_image(imgs[i], nq))) return st;
+
+    tdct_plan* p = new (std::nothrow) tdct_plan();
+    if (!p) return TDCT_ENOMEM;
+    p->tune = tune;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        set_error("device query", e);
+        delete p;
+        return TDCT_EDEVICE;
+    }
+
+    // Quantiser constants per distinct (table, keep) pair.
+    std::map<std::pair<int, int>, int> qindex;
+    p->imgs.resize(n);
+    p->blk_off.assign((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        const tdct_image_desc& im = imgs[i];
+        const int keep = (im.op == TDCT_OP_ENCODE || im.op == TDCT_OP_ROUNDTRIP) ? im.keep : 64;
+        const int qt = im.op == TDCT_OP_FORWARD ? -1 : im.qtab;
+        auto key = std::make_pair(qt, keep);
+        auto it = qindex.find(key);
+        int qi;
+        if (it == qindex.end()) {
+            qi = (int)p->qcs.size();
+            QConst qc;
+            make_qconst(qt >= 0 ? &qtabs[qt] : nullptr, keep, &qc);
+            p->qcs.push_back(qc);
+            qindex.emplace(key, qi);
+        } else {
+            qi = it->second;
+        }
+        fill_desc(im.op, im.src, im.src_stride, im.w, im.h, im.coef, im.dst, im.dst_stride, qi,
+                  im.op == TDCT_OP_ROUNDTRIP && im.coef != nullptr, &p->imgs[i]);
+        p->blk_off[i + 1] = p->blk_off[i] + p->imgs[i].nblk;
+        p->pixels += (int64_t)im.w * im.h;
+    }
+    if (p->qcs.empty()) {
+        QConst qc;
+        make_qconst(nullptr, 64, &qc);
+        p->qcs.push_back(qc);
+    }
+    // Image-uniform tiles from each image's block range.
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t nb = p->blk_off[i + 1] - p->blk_off[i];
+        const int tb = tile_blocks(p->imgs[i].op);
+        for (int64_t f = 0; f < nb; f += tb) {
+            Tile t;
+            t.img = (uint32_t)i;
+            t.first_lo = (uint32_t)f;
+            t.first_hi = (uint32_t)(f >> 32);
+            t.count = (uint32_t)std::min<int64_t>(tb, nb - f);
+            p->tiles.push_back(t);
+        }
+    }
+    if (p->tiles.size() >= 0xffffffffull) {
+        delete p;
+        return TDCT_EINVAL;
+    }
+    // One device allocation: tiles | descriptors | constants (256-B aligned parts).
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t tb = up(p->tiles.size() * sizeof(Tile) + 16);
+    const size_t ib = up(p->imgs.size() * sizeof(ImgDesc) + 16);
+    const size_t qb = up(p->qcs.size() * sizeof(QConst));
+    p->dev_bytes = tb + ib + qb;
+    e = hipMalloc(&p->dev, p->dev_bytes);
+    if (e != hipSuccess) {
+        set_error("plan tables", e);
+        delete p;
+        return TDCT_ENOMEM;
+    }
+    char* base = (char*)p->dev;
+    p->tiles_d = (Tile*)base;
+    p->imgs_d = (ImgDesc*)(base + tb);
+    p->qcs_d = (QConst*)(base + tb + ib);
+    e = hipMemcpy(p->tiles_d, p->tiles.data(), p->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->imgs_d, p->imgs.data(), p->imgs.size() * sizeof(ImgDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->qcs_d, p->qcs.data(), p->qcs.size() * sizeof(QConst), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error("plan upload", e);
+        hipFree(p->dev);
+        delete p;
+        return TDCT_EDEVICE;
+    }
+    *out = p;
+    return TDCT_OK;
+}
+
+int tdct_batch_run(tdct_plan* p, void* stream) {
+    if (!p) return TDCT_EINVAL;
+    return run(p, (hipStream_t)stream);
+}
+
+int tdct_batch_graph(tdct_plan* p, void* stream) {
+    if (!p) return TDCT_EINVAL;
+    hipError_t e;
+    if (!p->exec) {
+        if (!p->capture_stream) {
+            e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                set_error("capture stream", e);
+                return TDCT_EDEVICE;
+            }
+        }
+        e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            set_error("begin capture", e);
+            return TDCT_EDEVICE;
+        }
+        int st = run(p, p->capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->capture_stream, &g);
+        if (st) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) {
+            set_error("end capture", e);
+            return TDCT_EDEVICE;
+        }
+        p->graph = g;
+        e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            set_error("graph instantiate", e);
+            free_graph(p);
+            return TDCT_EDEVICE;
+        }
+    }
+    e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("graph launch", e);
+        return TDCT_EDEVICE;
+    }
+    return TDCT_OK;
+}
+
+int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
+    if (!p || reps < 1) return TDCT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return TDCT_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return TDCT_EDEVICE;
+    }
+    const tdct_tune saved = p->tune;
+    tdct_tune winner = saved;
+    float best_ms = 1e30f;
+    int st = TDCT_OK;
+    const int wpgs[] = {1, 2, 4, 8};
+    const int gpcs[] = {1, 2, 4, 8, 16, 32};
+    const int tws[] = {1, 2};
+    for (int wpg : wpgs)
+        for (int gpc : gpcs)
+            for (int tw : tws) {
+                if (wpg * gpc > 32) continue;  // at most 32 waves per CU are resident
+                tdct_tune t{};
+                t.waves_per_group = wpg;
+                t.groups_per_cu = gpc;
+                t.tile_waves = tw;
+                p->tune = t;
+                if ((st = run(p, s))) goto done;  // warm-up
+                std::vector<float> ms;
+                for (int r = 0; r < reps; ++r) {
+                    hipEventRecord(e0, s);
+                    if ((st = run(p, s))) goto done;
+                    hipEventRecord(e1, s);
+                    hipError_t e = hipEventSynchronize(e1);
+                    if (e != hipSuccess) {
+                        set_error("autotune sync", e);
+                        st = TDCT_EDEVICE;
+                        goto done;
+                    }
+                    float m = 0;
+                    hipEventElapsedTime(&m, e0, e1);
+                    ms.push_back(m);
+                }
+                std::sort(ms.begin(), ms.end());
+                const float med = ms[ms.size() / 2];
+                if (med < best_ms) {
+                    best_ms = med;
+                    winner = t;
+                }
+            }
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) {
+        p->tune = saved;
+        return st;
+    }
+    free_graph(p);  // a captured graph holds the launch shape it was made with
+    p->tune = winner;
+    if (best) *best = winner;
+    return TDCT_OK;
+}
+
+int tdct_plan_info_get(const tdct_plan* p, tdct_plan_info* out) {
+    if (!p || !out) return TDCT_EINVAL;
+    out->images = (int64_t)p->imgs.size();
+    out->blocks = p->blk_off.empty() ? 0 : p->blk_off.back();
+    out->tiles = (int64_t)p->tiles.size();
+    out->pixels = p->pixels;
+    out->table_bytes = (int64_t)p->dev_bytes;
+    out->tune = p->tune;
+    return TDCT_OK;
+}
+
+void tdct_plan_free(tdct_plan* p) {
+    if (!p) return;
+    free_graph(p);
+    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+    if (p->dev) hipFree(p->dev);
+    delete p;
+}
+
+int tdct_run_per_image(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs, int32_t nq,
+                       void* stream) {
+    if (n < 0 || (n > 0 && !imgs) || nq < 0 || (nq > 0 && !qtabs)) return TDCT_EINVAL;
+    int st;
+    for (int32_t k = 0; k < nq; ++k)
+        if ((st = validate_q(&qtabs[k]))) return st;
+    for (int32_t i = 0; i < n; ++i)
+        if ((st = validate_image(imgs[i], nq))) return st;
+    for (int32_t i = 0; i < n; ++i) {
+        const tdct_image_desc& im = imgs[i];
+        const int keep = (im.op == TDCT_OP_ENCODE || im.op == TDCT_OP_ROUNDTRIP) ? im.keep : 64;
+        QConst qc;
+        make_qconst(im.op == TDCT_OP_FORWARD ? nullptr : &qtabs[im.qtab], keep, &qc);
+        ImgDesc d;
+        fill_desc(im.op, im.src, im.src_stride, im.w, im.h, im.coef, im.dst, im.dst_stride, 0,
+                  im.op == TDCT_OP_ROUNDTRIP && im.coef != nullptr, &d);
+        if ((st = launch_plain_op(im.op, d, qc, (hipStream_t)stream))) return st;
+    }
+    return TDCT_OK;
+}
+
+}  // extern "C"

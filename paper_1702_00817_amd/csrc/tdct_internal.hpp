@@ -1,0 +1,25 @@
+// Host-side interfaces shared by the plain calls, the batch planner and the
+// server (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tdct.h"
+#include "tdct_device.hpp"
+
+namespace tdct {
+
+void set_error(const char* what, hipError_t e);
+int check_launch(const char* what);
+int validate_plane(const void* p, int64_t stride, int32_t w, int32_t h);
+int validate_q(const tdct_qtable* Q);
+void make_qconst(const tdct_qtable* Q, int keep, QConst* out);
+int image_flags(const ImgDesc& d);
+int fill_desc(int op, const uint8_t* src, int64_t src_stride, int32_t w, int32_t h, void* coef,
+              uint8_t* dst, int64_t dst_stride, int32_t qidx, bool write_coef, ImgDesc* d);
+int launch_plain_op(int op, const ImgDesc& d, const QConst& qc, hipStream_t stream);
+int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
+                 const tdct_tune& tune, int num_cus, hipStream_t stream);
+
+}  // namespace tdct

@@ -1,0 +1,571 @@
+// HIP kernels of the codec for gfx950 (CDNA4), and the plain C-ABI calls.
+//
+// Thread mapping. Every lane owns whole 8x8 blocks, so both 1-D passes of
+// the separable transform (Section 3) run in registers without cross-lane
+// traffic:
+//  * encoder-side ops: a lane owns two blocks that are adjacent in raster
+//    order (normally horizontal neighbours) and keeps pixel (r, c) of both as
+//    one packed int16 pair, so every v_pk_add/v_pk_sub does the butterfly of
+//    Section 2 for both blocks (the whole 2-D forward transform costs 1.75
+//    VALU ops per pixel). Unshifted pixels keep every intermediate within
+//    16 bits (|sum| <= 64 * 255), and the level shift -128 moves only the DC
+//    term (rows 1..7 of T sum to zero), by -8192;
+//  * the decoder: a lane owns one block in int32, because with Q <= 4095 an
+//    arbitrary int16 input needs 32-bit intermediates.
+// A wave-tile is up to 128 (encoder) or 64 (decoder) consecutive blocks of
+// one image; rows of adjacent blocks are contiguous, so the pixel-side loads
+// and stores of a wave cover whole 512- or 1024-byte runs of a row.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "tdct.h"
+#include "tdct_device.hpp"
+#include "tdct_internal.hpp"
+
+namespace tdct {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// Pack two int32 values (known to fit 16 bits) into one dword, low first.
+__device__ __forceinline__ uint32_t pack16(int lo, int hi) {
+    return __builtin_amdgcn_perm((uint32_t)hi, (uint32_t)lo, 0x05040100u);
+}
+
+// Pack four values in [0, 255] into one dword, first in the low byte.
+__device__ __forceinline__ uint32_t pack8(int b0, int b1, int b2, int b3) {
+    uint32_t lo = __builtin_amdgcn_perm((uint32_t)b1, (uint32_t)b0, 0x0c0c0400u);
+    uint32_t hi = __builtin_amdgcn_perm((uint32_t)b3, (uint32_t)b2, 0x04000c0cu);
+    return lo | hi;
+}
+
+// ---- pixel loads ---------------------------------------------------------
+
+// Rows of block a (A[r][0..1]) and block b (B[r][0..1]) as little-endian
+// dwords. `pair16`: b is a's right neighbour and one 16-byte load per row
+// fetches both.
+struct PixRows {
+    uint32_t A[8][2];
+    uint32_t B[8][2];
+};
+
+__device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int flags,
+                                           uint32_t (&R)[8][2]) {
+    if (flags & F_SRC8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            uint2 v = *reinterpret_cast<const uint2*>(p + r * stride);
+            R[r][0] = v.x;
+            R[r][1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint8_t* q = p + r * stride;
+            R[r][0] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) |
+                      ((uint32_t)q[3] << 24);
+            R[r][1] = (uint32_t)q[4] | ((uint32_t)q[5] << 8) | ((uint32_t)q[6] << 16) |
+                      ((uint32_t)q[7] << 24);
+        }
+    }
+}
+
+__device__ __forceinline__ void store_rows8(uint8_t* p, int64_t stride, int flags,
+                                            const uint32_t (&R)[8][2]) {
+    if (flags & F_DST8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            *reinterpret_cast<uint2*>(p + r * stride) = make_uint2(R[r][0], R[r][1]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            uint8_t* q = p + r * stride;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                q[c] = (uint8_t)(R[r][0] >> (8 * c));
+                q[4 + c] = (uint8_t)(R[r][1] >> (8 * c));
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ const uint8_t* block_ptr(const uint8_t* base, int64_t stride,
+                                                    uint32_t nbx, uint32_t b) {
+    uint32_t by = b / nbx;
+    uint32_t bx = b - by * nbx;
+    return base + (int64_t)(8 * by) * stride + 8 * bx;
+}
+
+// ---- decoder core ----------------------------------------------------------
+
+// Dequantise + inverse transform of one block whose int16 coefficients sit in
+// 32 dwords (natural order, two per dword), producing 8 rows of 8 pixels.
+template <class QC>
+__device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC& qc,
+                                             uint32_t (&px)[8][2]) {
+    int W[64];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        int lo = (int)(short)(qp[k] & 0xffffu);
+        int hi = (int)qp[k] >> 16;
+        W[2 * k] = lo * qc.Q[2 * k];
+        W[2 * k + 1] = hi * qc.Q[2 * k + 1];
+    }
+    // +32 rounds floor((S + 32) / 64); +8192 = 64 * 128 undoes the level
+    // shift. Column 0 of T^t is all ones, so adding both to W'_00 adds them
+    // to every S_rc.
+    W[0] += 32 + 8192;
+    inv8x8(W);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        int p[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) p[c] = min(max(W[8 * r + c] >> 6, 0), 255);
+        px[r][0] = pack8(p[0], p[1], p[2], p[3]);
+        px[r][1] = pack8(p[4], p[5], p[6], p[7]);
+    }
+}
+
+// ---- encoder tile ------------------------------------------------------------
+
+template <int OP, class QC>
+__device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, int lane) {
+    const uint32_t la = 2u * (uint32_t)lane, lb = la + 1u;
+    const bool va = la < count, vb = lb < count;
+    if (!va) return;
+    const uint32_t nbx = (uint32_t)d.nbx;
+    const uint32_t ba = first + la, bb = first + lb;
+
+    uint32_t A[8][2], B[8][2];
+    const uint8_t* pa = block_ptr(d.src, d.src_stride, nbx, ba);
+    if (d.flags & F_SRC16) {
+        // b is a's right neighbour in the same row, 16-byte aligned.
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            uint4 v = *reinterpret_cast<const uint4*>(pa + r * d.src_stride);
+            A[r][0] = v.x;
+            A[r][1] = v.y;
+            B[r][0] = v.z;
+            B[r][1] = v.w;
+        }
+    } else {
+        load_rows8(pa, d.src_stride, d.flags, A);
+        if (vb) {
+            load_rows8(block_ptr(d.src, d.src_stride, nbx, bb), d.src_stride, d.flags, B);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) B[r][0] = B[r][1] = 0x80808080u;
+        }
+    }
+
+    // Pixel (r, c) of both blocks as a packed (a, b) int16 pair.
+    s16x2 v[64];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t k = (uint32_t)(c & 3);
+            const uint32_t sel = k | (0x0cu << 8) | ((4u + k) << 16) | (0x0cu << 24);
+            v[8 * r + c] = as_s16x2(__builtin_amdgcn_perm(B[r][c >> 2], A[r][c >> 2], sel));
+        }
+    }
+    fwd8x8(v);
+    v[0] -= (s16x2){8192, 8192};
+
+    if constexpr (OP == OP_FORWARD) {
+        int32_t* oa = reinterpret_cast<int32_t*>(d.coef) + (int64_t)ba * 64;
+#pragma unroll
+        for (int k = 0; k < 64; k += 4)
+            *reinterpret_cast<int4*>(oa + k) = make_int4(v[k].x, v[k + 1].x, v[k + 2].x, v[k + 3].x);
+        if (vb) {
+            int32_t* ob = reinterpret_cast<int32_t*>(d.coef) + (int64_t)bb * 64;
+#pragma unroll
+            for (int k = 0; k < 64; k += 4)
+                *reinterpret_cast<int4*>(ob + k) =
+                    make_int4(v[k].y, v[k + 1].y, v[k + 2].y, v[k + 3].y);
+        }
+        return;
+    } else if constexpr (OP == OP_ENCODE_I8ZZ) {
+        uint32_t qa[16], qb[16];
+#pragma unroll
+        for (int n = 0; n < 64; n += 4) {
+            int a4[4], b4[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = kZigzag.order[n + t];
+                a4[t] = min(max(quant_f32(v[k].x, qc.r[k]), -128), 127) & 0xff;
+                b4[t] = min(max(quant_f32(v[k].y, qc.r[k]), -128), 127) & 0xff;
+            }
+            qa[n / 4] = pack8(a4[0], a4[1], a4[2], a4[3]);
+            qb[n / 4] = pack8(b4[0], b4[1], b4[2], b4[3]);
+        }
+        int8_t* oa = reinterpret_cast<int8_t*>(d.coef) + (int64_t)ba * 64;
+#pragma unroll
+        for (int k = 0; k < 16; k += 4)
+            *reinterpret_cast<uint4*>(oa + 4 * k) = make_uint4(qa[k], qa[k + 1], qa[k + 2], qa[k + 3]);
+        if (vb) {
+            int8_t* ob = reinterpret_cast<int8_t*>(d.coef) + (int64_t)bb * 64;
+#pragma unroll
+            for (int k = 0; k < 16; k += 4)
+                *reinterpret_cast<uint4*>(ob + 4 * k) =
+                    make_uint4(qb[k], qb[k + 1], qb[k + 2], qb[k + 3]);
+        }
+        return;
+    } else {
+        // OP_ENCODE / OP_ROUNDTRIP: int16 coefficients, natural order.
+        uint32_t qa[32], qb[32];
+#pragma unroll
+        for (int k = 0; k < 64; k += 2) {
+            qa[k / 2] = pack16(quant_f32(v[k].x, qc.r[k]), quant_f32(v[k + 1].x, qc.r[k + 1]));
+            qb[k / 2] = pack16(quant_f32(v[k].y, qc.r[k]), quant_f32(v[k + 1].y, qc.r[k + 1]));
+        }
+        const bool write_coef = (OP == OP_ENCODE) || (d.flags & F_COEF);
+        if (write_coef) {
+            int16_t* oa = reinterpret_cast<int16_t*>(d.coef) + (int64_t)ba * 64;
+#pragma unroll
+            for (int k = 0; k < 32; k += 4)
+                *reinterpret_cast<uint4*>(oa + 2 * k) =
+                    make_uint4(qa[k], qa[k + 1], qa[k + 2], qa[k + 3]);
+            if (vb) {
+                int16_t* ob = reinterpret_cast<int16_t*>(d.coef) + (int64_t)bb * 64;
+#pragma unroll
+                for (int k = 0; k < 32; k += 4)
+                    *reinterpret_cast<uint4*>(ob + 2 * k) =
+                        make_uint4(qb[k], qb[k + 1], qb[k + 2], qb[k + 3]);
+            }
+        }
+        if constexpr (OP == OP_ROUNDTRIP) {
+            uint32_t px[8][2];
+            decode_block(qa, qc, px);
+            store_rows8(const_cast<uint8_t*>(block_ptr(d.dst, d.dst_stride, nbx, ba)),
+                        d.dst_stride, d.flags, px);
+            if (vb) {
+                decode_block(qb, qc, px);
+                store_rows8(const_cast<uint8_t*>(block_ptr(d.dst, d.dst_stride, nbx, bb)),
+                            d.dst_stride, d.flags, px);
+            }
+        }
+    }
+}
+
+// ---- decoder tile -----------------------------------------------------------
+
+template <class QC>
+__device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, int lane) {
+    if ((uint32_t)lane >= count) return;
+    const uint32_t b = first + (uint32_t)lane;
+    const int16_t* src = reinterpret_cast<const int16_t*>(d.coef) + (int64_t)b * 64;
+    uint32_t qp[32];
+#pragma unroll
+    for (int k = 0; k < 32; k += 4) {
+        uint4 v = *reinterpret_cast<const uint4*>(src + 2 * k);
+        qp[k] = v.x;
+        qp[k + 1] = v.y;
+        qp[k + 2] = v.z;
+        qp[k + 3] = v.w;
+    }
+    uint32_t px[8][2];
+    decode_block(qp, qc, px);
+    store_rows8(const_cast<uint8_t*>(block_ptr(d.dst, d.dst_stride, (uint32_t)d.nbx, b)),
+                d.dst_stride, d.flags, px);
+}
+
+template <int OP, class QC>
+__device__ __forceinline__ void run_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, int lane) {
+    if constexpr (OP == OP_DECODE)
+        dec_tile(d, qc, first, count, lane);
+    else
+        enc_tile<OP>(d, qc, first, count, lane);
+}
+
+// ---- kernels -----------------------------------------------------------------
+
+// One image, quantiser constants in the kernel arguments. Wave w handles
+// tiles w, w + nwaves, ... of the image.
+template <int OP>
+__global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QConst qc,
+                                                    uint32_t ntiles) {
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpg + (threadIdx.x >> 6));
+    const uint32_t nwaves = gridDim.x * wpg;
+    const int lane = threadIdx.x & 63;
+    constexpr uint32_t TB = OP == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
+    const uint32_t nblk = (uint32_t)d.nblk;
+    for (uint32_t t = wave; t < ntiles; t += nwaves) {
+        const uint32_t first = t * TB;
+        const uint32_t count = min(TB, nblk - first);
+        run_tile<OP>(d, qc, first, count, lane);
+    }
+}
+
+// Many images: tiles come from a table; each tile names its image, whose
+// descriptor and quantiser constants are read with scalar loads (the tile is
+// image-uniform, so they are the same for the whole wave).
+__global__ __launch_bounds__(1024) void batch_kernel(const Tile* __restrict__ tiles,
+                                                     const ImgDesc* __restrict__ imgs,
+                                                     const QConst* __restrict__ qcs,
+                                                     uint32_t ntiles, uint32_t tile_waves) {
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpg + (threadIdx.x >> 6));
+    const uint32_t nwaves = gridDim.x * wpg;
+    const int lane = threadIdx.x & 63;
+    // A wave takes `tile_waves` consecutive tiles per step.
+    for (uint32_t t0 = wave * tile_waves; t0 < ntiles; t0 += nwaves * tile_waves) {
+        const uint32_t tend = min(t0 + tile_waves, ntiles);
+        for (uint32_t t = t0; t < tend; ++t) {
+            const Tile tl = tiles[t];
+            const ImgDesc& d = imgs[tl.img];
+            const QConst& qc = qcs[d.qidx];
+            switch (d.op) {
+                case OP_ENCODE: run_tile<OP_ENCODE>(d, qc, tl.first_lo, tl.count, lane); break;
+                case OP_DECODE: run_tile<OP_DECODE>(d, qc, tl.first_lo, tl.count, lane); break;
+                case OP_ROUNDTRIP: run_tile<OP_ROUNDTRIP>(d, qc, tl.first_lo, tl.count, lane); break;
+                case OP_ENCODE_I8ZZ: run_tile<OP_ENCODE_I8ZZ>(d, qc, tl.first_lo, tl.count, lane); break;
+                default: run_tile<OP_FORWARD>(d, qc, tl.first_lo, tl.count, lane); break;
+            }
+        }
+    }
+}
+
+// Sum of squared differences; one 64-bit atomic per workgroup.
+__global__ __launch_bounds__(256) void sse_kernel(const uint8_t* a, int64_t as, const uint8_t* b,
+                                                  int64_t bs, int32_t w, int32_t h,
+                                                  unsigned long long* out) {
+    unsigned long long acc = 0;
+    const int64_t n = (int64_t)w * h;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / w, x = i - y * w;
+        const int dd = (int)a[y * as + x] - (int)b[y * bs + x];
+        acc += (unsigned long long)(dd * dd);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += part[k];
+        atomicAdd(out, s);
+    }
+}
+
+__global__ void zero_u64(unsigned long long* p) { *p = 0ull; }
+
+// ---- host side ---------------------------------------------------------------
+
+static thread_local char g_err[256];
+
+void set_error(const char* what, hipError_t e) {
+    snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(what, e);
+        return TDCT_EDEVICE;
+    }
+    return TDCT_OK;
+}
+
+int validate_plane(const void* p, int64_t stride, int32_t w, int32_t h) {
+    if (w <= 0 || h <= 0 || (w & 7) || (h & 7) || w > TDCT_MAX_SIDE || h > TDCT_MAX_SIDE)
+        return TDCT_EDIM;
+    if (!p || stride < w) return TDCT_EINVAL;
+    return TDCT_OK;
+}
+
+int validate_q(const tdct_qtable* Q) {
+    if (!Q) return TDCT_EINVAL;
+    for (int k = 0; k < 64; ++k)
+        if (Q->q[k] < 1 || Q->q[k] > TDCT_QMAX) return TDCT_EQTAB;
+    return TDCT_OK;
+}
+
+void make_qconst(const tdct_qtable* Q, int keep, QConst* out) {
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * i + j;
+            const int q = Q ? Q->q[k] : 1;
+            out->r[k] = quant_recip(q, kShift(i, j), kZigzag.rank[k] < keep);
+            out->Q[k] = q;
+        }
+}
+
+int image_flags(const ImgDesc& d) {
+    int f = 0;
+    const uintptr_t s = (uintptr_t)d.src, t = (uintptr_t)d.dst;
+    if (d.src && (s % 8 == 0) && (d.src_stride % 8 == 0)) f |= F_SRC8;
+    if (d.src && (s % 16 == 0) && (d.src_stride % 16 == 0) && (d.nbx % 2 == 0)) f |= F_SRC16;
+    if (d.dst && (t % 8 == 0) && (d.dst_stride % 8 == 0)) f |= F_DST8;
+    return f;
+}
+
+template <int OP>
+static int launch_plain(const ImgDesc& d, const QConst& qc, hipStream_t stream) {
+    constexpr uint32_t TB = OP == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
+    const uint32_t ntiles = (uint32_t)((d.nblk + TB - 1) / TB);
+    const uint32_t wpg = 4;
+    const uint32_t grid = (ntiles + wpg - 1) / wpg;
+    hipLaunchKernelGGL(plain_kernel<OP>, dim3(grid), dim3(64 * wpg), 0, stream, d, qc, ntiles);
+    return check_launch("plain kernel launch");
+}
+
+int launch_plain_op(int op, const ImgDesc& d, const QConst& qc, hipStream_t stream) {
+    switch (op) {
+        case OP_ENCODE: return launch_plain<OP_ENCODE>(d, qc, stream);
+        case OP_DECODE: return launch_plain<OP_DECODE>(d, qc, stream);
+        case OP_ROUNDTRIP: return launch_plain<OP_ROUNDTRIP>(d, qc, stream);
+        case OP_ENCODE_I8ZZ: return launch_plain<OP_ENCODE_I8ZZ>(d, qc, stream);
+        case OP_FORWARD: return launch_plain<OP_FORWARD>(d, qc, stream);
+    }
+    return TDCT_EINVAL;
+}
+
+int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
+                 const tdct_tune& tune, int num_cus, hipStream_t stream) {
+    if (ntiles == 0) return TDCT_OK;
+    const uint32_t wpg = (uint32_t)tune.waves_per_group;
+    const uint32_t tw = (uint32_t)tune.tile_waves;
+    const uint32_t steps = (ntiles + tw - 1) / tw;
+    uint32_t grid = (uint32_t)num_cus * (uint32_t)tune.groups_per_cu;
+    const uint32_t need = (steps + wpg - 1) / wpg;
+    if (grid > need) grid = need;
+    if (grid == 0) grid = 1;
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(64 * wpg), 0, stream, tiles, imgs, qcs,
+                       ntiles, tw);
+    return check_launch("batch kernel launch");
+}
+
+int fill_desc(int op, const uint8_t* src, int64_t src_stride, int32_t w, int32_t h, void* coef,
+              uint8_t* dst, int64_t dst_stride, int32_t qidx, bool write_coef, ImgDesc* d) {
+    d->src = src;
+    d->dst = dst;
+    d->coef = coef;
+    d->src_stride = src_stride;
+    d->dst_stride = dst_stride;
+    d->nbx = w / 8;
+    d->nblk = (int64_t)(w / 8) * (h / 8);
+    d->op = op;
+    d->qidx = qidx;
+    d->flags = image_flags(*d) | (write_coef ? F_COEF : 0);
+    return TDCT_OK;
+}
+
+}  // namespace tdct
+
+using namespace tdct;
+
+static int coef_aligned(const void* p) { return p && ((uintptr_t)p % 16 == 0); }
+
+extern "C" {
+
+int tdct_forward(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h, int32_t* coef,
+                 void* stream) {
+    int st = validate_plane(src, src_stride, w, h);
+    if (st) return st;
+    if (!coef_aligned(coef)) return TDCT_EINVAL;
+    ImgDesc d;
+    fill_desc(OP_FORWARD, src, src_stride, w, h, coef, nullptr, 0, 0, false, &d);
+    QConst qc;
+    make_qconst(nullptr, 64, &qc);
+    return launch_plain_op(OP_FORWARD, d, qc, (hipStream_t)stream);
+}
+
+int tdct_quantise(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
+                  const tdct_qtable* Q, int32_t keep, int16_t* q, void* stream) {
+    int st = validate_plane(src, src_stride, w, h);
+    if (st) return st;
+    if ((st = validate_q(Q))) return st;
+    if (!coef_aligned(q) || keep < 1 || keep > 64) return TDCT_EINVAL;
+    ImgDesc d;
+    fill_desc(OP_ENCODE, src, src_stride, w, h, q, nullptr, 0, 0, true, &d);
+    QConst qc;
+    make_qconst(Q, keep, &qc);
+    return launch_plain_op(OP_ENCODE, d, qc, (hipStream_t)stream);
+}
+
+int tdct_inverse(const int16_t* q, const tdct_qtable* Q, int32_t w, int32_t h, uint8_t* dst,
+                 int64_t dst_stride, void* stream) {
+    int st = validate_plane(dst, dst_stride, w, h);
+    if (st) return st;
+    if ((st = validate_q(Q))) return st;
+    if (!coef_aligned(q)) return TDCT_EINVAL;
+    ImgDesc d;
+    fill_desc(OP_DECODE, nullptr, 0, w, h, const_cast<int16_t*>(q), dst, dst_stride, 0, false, &d);
+    QConst qc;
+    make_qconst(Q, 64, &qc);
+    return launch_plain_op(OP_DECODE, d, qc, (hipStream_t)stream);
+}
+
+int tdct_roundtrip(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
+                   const tdct_qtable* Q, int32_t keep, int16_t* q_or_null, uint8_t* dst,
+                   int64_t dst_stride, void* stream) {
+    int st = validate_plane(src, src_stride, w, h);
+    if (st) return st;
+    if ((st = validate_plane(dst, dst_stride, w, h))) return st;
+    if ((st = validate_q(Q))) return st;
+    if (keep < 1 || keep > 64) return TDCT_EINVAL;
+    if (q_or_null && !coef_aligned(q_or_null)) return TDCT_EINVAL;
+    ImgDesc d;
+    fill_desc(OP_ROUNDTRIP, src, src_stride, w, h, q_or_null, dst, dst_stride, 0,
+              q_or_null != nullptr, &d);
+    QConst qc;
+    make_qconst(Q, keep, &qc);
+    return launch_plain_op(OP_ROUNDTRIP, d, qc, (hipStream_t)stream);
+}
+
+int tdct_quantise_i8_zigzag(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
+                            const tdct_qtable* Q, int8_t* out, void* stream) {
+    int st = validate_plane(src, src_stride, w, h);
+    if (st) return st;
+    if ((st = validate_q(Q))) return st;
+    if (!coef_aligned(out)) return TDCT_EINVAL;
+    ImgDesc d;
+    fill_desc(OP_ENCODE_I8ZZ, src, src_stride, w, h, out, nullptr, 0, 0, true, &d);
+    QConst qc;
+    make_qconst(Q, 64, &qc);
+    return launch_plain_op(OP_ENCODE_I8ZZ, d, qc, (hipStream_t)stream);
+}
+
+int tdct_sse(const uint8_t* a, int64_t a_stride, const uint8_t* b, int64_t b_stride, int32_t w,
+             int32_t h, uint64_t* sse_dev, void* stream) {
+    int st = validate_plane(a, a_stride, w, h);
+    if (st) return st;
+    if ((st = validate_plane(b, b_stride, w, h))) return st;
+    if (!sse_dev) return TDCT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, (unsigned long long*)sse_dev);
+    const int64_t n = (int64_t)w * h;
+    int64_t grid = (n + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(sse_kernel, dim3((uint32_t)grid), dim3(256), 0, s, a, a_stride, b, b_stride,
+                       w, h, (unsigned long long*)sse_dev);
+    return check_launch("sse kernel launch");
+}
+
+const char* tdct_strerror(int status) {
+    switch (status) {
+        case TDCT_OK: return "ok";
+        case TDCT_EINVAL: return "invalid argument (null pointer, stride, alignment, keep or op)";
+        case TDCT_EDIM: return "width/height not a positive multiple of 8 (or above 65536)";
+        case TDCT_EQTAB: return "quantisation table entry outside [1, 4095]";
+        case TDCT_ENOMEM: return "out of device memory or request larger than the budget";
+        case TDCT_EDEVICE: return "HIP runtime error";
+        case TDCT_EBUSY: return "not ready";
+        case TDCT_ENOTFOUND: return "unknown ticket";
+    }
+    return "unknown status";
+}
+
+const char* tdct_last_error(void) { return g_err; }
+
+}  // extern "C"

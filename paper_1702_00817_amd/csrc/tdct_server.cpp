@@ -1,0 +1,635 @@
+// Serving form: a request loop in front of the persistent batch kernel.
+//
+// submit() only records a request. One scheduler thread owns everything
+// else, in this order on every pass:
+//   1. completion: a stream slot whose event has fired marks its requests
+//      done (the host clock at that moment is the completion time);
+//   2. admission: waiting requests, oldest first, reserve their output bytes
+//      in the device arena; the first that does not fit stops admission
+//      (FIFO), so a large request is never starved by smaller ones;
+//   3. launch: while a stream slot is free and admitted requests exist, up
+//      to max_batch of them are cut into image-uniform tiles, the tables go
+//      through the slot's pinned staging buffer to its device tables, and
+//      one persistent kernel launch on the slot's stream serves them all.
+// Several slots may be in flight at once, so requests that arrive while
+// others run are admitted and launched as memory and slots free up, and their
+// kernels overlap on the device (continuous batching). With batching = 0 the
+// same loop launches each request on its own (the per-image baseline).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tdct.h"
+#include "tdct_internal.hpp"
+
+using namespace tdct;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) in 256-byte granules; adjacent free
+// ranges are merged on release.
+class Arena {
+  public:
+    explicit Arena(int64_t size) : size_(size) {
+        if (size > 0) free_[0] = size;
+    }
+    int64_t alloc(int64_t n) {
+        n = round(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                const int64_t off = it->first, rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                used_ += n;
+                high_ = std::max(high_, used_);
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t n) {
+        n = round(n);
+        used_ -= n;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + n == next->first) {
+            n += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += n;
+                return;
+            }
+        }
+        free_[off] = n;
+    }
+    static int64_t round(int64_t n) { return (n + 255) & ~int64_t(255); }
+    int64_t size() const { return size_; }
+    int64_t used() const { return used_; }
+    int64_t high() const { return high_; }
+
+  private:
+    int64_t size_, used_ = 0, high_ = 0;
+    std::map<int64_t, int64_t> free_;
+};
+
+struct Req {
+    tdct_request r{};
+    int64_t out_bytes = 0;
+    int64_t arena_off = -1;
+    double submit_us = 0, done_us = 0;
+    int32_t status = TDCT_EBUSY;
+    int32_t batch_size = 0;
+    bool release_on_done = false;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    double launched_us = 0;
+    double fake_done_us = 0;
+    bool fake_fail = false;
+    std::vector<uint64_t> tickets;
+    void* dev = nullptr;  // tiles | descriptors | constants
+    size_t dev_cap = 0;
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+};
+
+}  // namespace
+
+struct tdct_server {
+    tdct_server_cfg cfg{};
+    bool fake = false;
+    int num_cus = 0;
+    Arena* arena = nullptr;
+    char* arena_base = nullptr;
+    std::mutex mu;
+    std::condition_variable wake;   // scheduler
+    std::condition_variable done;   // waiters
+    std::deque<uint64_t> waiting;   // submitted, no output memory yet
+    std::deque<uint64_t> admitted;  // output reserved, not launched
+    std::unordered_map<uint64_t, Req> reqs;
+    std::vector<Slot> slots;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    int64_t in_flight = 0;  // submitted and not completed
+    int64_t batches = 0;
+    int64_t batch_reqs = 0;
+    tdct_stats st{};
+    std::vector<double> lat;
+    double busy_since = -1;
+    Clock::time_point t0;
+    char err[256] = {0};
+
+    double now_us() const {
+        return std::chrono::duration<double, std::micro>(Clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+int64_t output_bytes(const tdct_request& r) {
+    const int64_t px = (int64_t)r.w * r.h;
+    return r.op == TDCT_OP_ENCODE ? 2 * px : px;
+}
+
+int validate_request(const tdct_request& r) {
+    if (r.op != TDCT_OP_ENCODE && r.op != TDCT_OP_DECODE) return TDCT_EINVAL;
+    if (r.w <= 0 || r.h <= 0 || (r.w & 7) || (r.h & 7) || r.w > TDCT_MAX_SIDE || r.h > TDCT_MAX_SIDE)
+        return TDCT_EDIM;
+    if (!r.input) return TDCT_EINVAL;
+    if (r.op == TDCT_OP_ENCODE) {
+        if (r.in_stride < r.w) return TDCT_EINVAL;
+        if (r.keep < 1 || r.keep > 64) return TDCT_EINVAL;
+    } else if ((uintptr_t)r.input % 16) {
+        return TDCT_EINVAL;
+    }
+    return validate_q(&r.Q);
+}
+
+// Grows a slot's device and pinned buffers to `bytes` (rarely: capacity
+// doubles). Called without the server lock, by the scheduler thread only.
+int ensure_capacity(tdct_server* s, Slot& sl, size_t bytes) {
+    if (s->fake) return TDCT_OK;
+    if (bytes > sl.dev_cap) {
+        size_t cap = std::max(bytes, sl.dev_cap * 2);
+        if (sl.dev) hipFree(sl.dev);
+        sl.dev = nullptr;
+        sl.dev_cap = 0;
+        hipError_t e = hipMalloc(&sl.dev, cap);
+        if (e != hipSuccess) {
+            set_error("server tables", e);
+            return TDCT_ENOMEM;
+        }
+        sl.dev_cap = cap;
+    }
+    if (bytes > sl.pinned_cap) {
+        size_t cap = std::max(bytes, sl.pinned_cap * 2);
+        if (sl.pinned) hipHostFree(sl.pinned);
+        sl.pinned = nullptr;
+        sl.pinned_cap = 0;
+        hipError_t e = hipHostMalloc(&sl.pinned, cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_error("server staging", e);
+            return TDCT_ENOMEM;
+        }
+        sl.pinned_cap = cap;
+    }
+    return TDCT_OK;
+}
+
+struct BatchItem {
+    uint64_t ticket;
+    tdct_request r;
+    void* out;
+};
+
+// Builds tables for the batch and launches it on the slot. No lock held.
+int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>& items) {
+    if (s->fake) return TDCT_OK;
+    const int n = (int)items.size();
+    if (!s->cfg.batching) {
+        // Per-request plain launches (comparison mode): one request per slot.
+        for (const BatchItem& it : items) {
+            const tdct_request& r = it.r;
+            QConst qc;
+            make_qconst(&r.Q, r.op == TDCT_OP_ENCODE ? r.keep : 64, &qc);
+            ImgDesc d;
+            if (r.op == TDCT_OP_ENCODE)
+                fill_desc(OP_ENCODE, (const uint8_t*)r.input, r.in_stride, r.w, r.h, it.out, nullptr,
+                          0, 0, true, &d);
+            else
+                fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(r.input),
+                          (uint8_t*)it.out, r.w, 0, false, &d);
+            int st = launch_plain_op(d.op, d, qc, sl.stream);
+            if (st) return st;
+        }
+    } else {
+        std::vector<ImgDesc> imgs((size_t)n);
+        std::vector<QConst> qcs((size_t)n);
+        std::vector<Tile> tiles;
+        for (int i = 0; i < n; ++i) {
+            const tdct_request& r = items[i].r;
+            make_qconst(&r.Q, r.op == TDCT_OP_ENCODE ? r.keep : 64, &qcs[i]);
+            if (r.op == TDCT_OP_ENCODE)
+                fill_desc(OP_ENCODE, (const uint8_t*)r.input, r.in_stride, r.w, r.h, items[i].out,
+                          nullptr, 0, i, true, &imgs[i]);
+            else
+                fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(r.input),
+                          (uint8_t*)items[i].out, r.w, i, false, &imgs[i]);
+            const int tb = tile_blocks(imgs[i].op);
+            for (int64_t f = 0; f < imgs[i].nblk; f += tb) {
+                Tile t;
+                t.img = (uint32_t)i;
+                t.first_lo = (uint32_t)f;
+                t.first_hi = 0;
+                t.count = (uint32_t)std::min<int64_t>(tb, imgs[i].nblk - f);
+                tiles.push_back(t);
+            }
+        }
+        auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+        const size_t tb = up(tiles.size() * sizeof(Tile)), ib = up(imgs.size() * sizeof(ImgDesc));
+        const size_t qb = up(qcs.size() * sizeof(QConst));
+        int st = ensure_capacity(s, sl, tb + ib + qb);
+        if (st) return st;
+        char* h = (char*)sl.pinned;
+        memcpy(h, tiles.data(), tiles.size() * sizeof(Tile));
+        memcpy(h + tb, imgs.data(), imgs.size() * sizeof(ImgDesc));
+        memcpy(h + tb + ib, qcs.data(), qcs.size() * sizeof(QConst));
+        hipError_t e = hipMemcpyAsync(sl.dev, sl.pinned, tb + ib + qb, hipMemcpyHostToDevice,
+                                      sl.stream);
+        if (e != hipSuccess) {
+            set_error("server table upload", e);
+            return TDCT_EDEVICE;
+        }
+        char* dbase = (char*)sl.dev;
+        st = launch_batch((const Tile*)dbase, (const ImgDesc*)(dbase + tb),
+                          (const QConst*)(dbase + tb + ib), (uint32_t)tiles.size(), s->cfg.tune,
+                          s->num_cus, sl.stream);
+        if (st) return st;
+    }
+    hipError_t e = hipEventRecord(sl.done, sl.stream);
+    if (e != hipSuccess) {
+        set_error("server event", e);
+        return TDCT_EDEVICE;
+    }
+    return TDCT_OK;
+}
+
+void finish_request(tdct_server* s, uint64_t t, int status, int batch_size, double now) {
+    auto it = s->reqs.find(t);
+    if (it == s->reqs.end()) return;
+    Req& q = it->second;
+    q.status = status;
+    q.done_us = now;
+    q.batch_size = batch_size;
+    s->in_flight--;
+    if (status == TDCT_OK) {
+        s->st.completed++;
+        s->st.pixels_done += (int64_t)q.r.w * q.r.h;
+        s->lat.push_back(now - q.submit_us);
+    } else {
+        s->st.failed++;
+    }
+    if ((q.release_on_done || status != TDCT_OK) && q.arena_off >= 0) {
+        s->arena->release(q.arena_off, q.out_bytes);
+        q.arena_off = -1;
+    }
+}
+
+void scheduler(tdct_server* s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    std::vector<BatchItem> items;
+    while (true) {
+        const double now = s->now_us();
+        // 1. completions
+        bool any_busy = false;
+        for (Slot& sl : s->slots) {
+            if (!sl.busy) continue;
+            bool fired;
+            int status = TDCT_OK;
+            if (s->fake) {
+                fired = now >= sl.fake_done_us;
+                if (sl.fake_fail) status = TDCT_EDEVICE;
+            } else {
+                hipError_t e = hipEventQuery(sl.done);
+                fired = e != hipErrorNotReady;
+                if (fired && e != hipSuccess) status = TDCT_EDEVICE;
+            }
+            if (fired) {
+                const int bs = (int)sl.tickets.size();
+                for (uint64_t t : sl.tickets) finish_request(s, t, status, bs, now);
+                sl.tickets.clear();
+                sl.busy = false;
+                s->done.notify_all();
+            } else {
+                any_busy = true;
+            }
+        }
+        if (any_busy) {
+            if (s->busy_since < 0) s->busy_since = now;
+        } else if (s->busy_since >= 0) {
+            s->st.busy_us += now - s->busy_since;
+            s->busy_since = -1;
+        }
+        // 2. admission, FIFO
+        while (!s->waiting.empty()) {
+            Req& q = s->reqs[s->waiting.front()];
+            const int64_t off = s->arena->alloc(q.out_bytes);
+            if (off < 0) break;
+            q.arena_off = off;
+            s->admitted.push_back(s->waiting.front());
+            s->waiting.pop_front();
+        }
+        s->st.arena_bytes_in_use = s->arena->used();
+        s->st.arena_high_water = s->arena->high();
+        // 3. launches
+        double next_deadline = -1;
+        for (Slot& sl : s->slots) {
+            if (sl.busy || s->admitted.empty()) continue;
+            const int maxb = s->cfg.batching ? std::max(1, s->cfg.max_batch) : 1;
+            const double oldest = s->reqs[s->admitted.front()].submit_us;
+            if (s->cfg.batching && s->cfg.max_wait_us > 0 && (int)s->admitted.size() < maxb &&
+                now - oldest < s->cfg.max_wait_us && !s->stop) {
+                next_deadline = oldest + s->cfg.max_wait_us;
+                break;
+            }
+            items.clear();
+            while (!s->admitted.empty() && (int)items.size() < maxb) {
+                const uint64_t t = s->admitted.front();
+                s->admitted.pop_front();
+                Req& q = s->reqs[t];
+                items.push_back({t, q.r, s->arena_base + q.arena_off});
+                sl.tickets.push_back(t);
+            }
+            sl.busy = true;
+            s->batches++;
+            s->batch_reqs += (int64_t)items.size();
+            sl.launched_us = now;
+            lk.unlock();
+            const int st = launch_batch_on_slot(s, sl, items);
+            lk.lock();
+            if (s->fake) {
+                sl.fake_done_us = s->now_us() + s->cfg.fake_device_us;
+                sl.fake_fail = s->cfg.fake_fail_every > 0 && (s->batches % s->cfg.fake_fail_every) == 0;
+            }
+            if (st) {
+                memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
+                const double t_now = s->now_us();
+                const int bs = (int)sl.tickets.size();
+                for (uint64_t t : sl.tickets) finish_request(s, t, st, bs, t_now);
+                sl.tickets.clear();
+                sl.busy = false;
+                s->done.notify_all();
+            }
+        }
+        if (s->stop && s->in_flight == 0) break;
+        // Sleep until something can change: a submit, a completion (polled),
+        // or the batching deadline.
+        bool busy_now = false;
+        for (Slot& sl : s->slots) busy_now |= sl.busy;
+        if (busy_now) {
+            s->wake.wait_for(lk, std::chrono::microseconds(5));
+        } else if (next_deadline >= 0) {
+            const double dt = std::max(1.0, next_deadline - s->now_us());
+            s->wake.wait_for(lk, std::chrono::microseconds((int64_t)dt));
+        } else if (s->admitted.empty() && s->waiting.empty() && !s->stop) {
+            s->wake.wait_for(lk, std::chrono::milliseconds(50));
+        } else if (!s->waiting.empty() && s->admitted.empty()) {
+            // waiting for arena space that only a release can free
+            s->wake.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+    if (s->busy_since >= 0) s->st.busy_us += s->now_us() - s->busy_since;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
+    if (!cfg || !out) return TDCT_EINVAL;
+    *out = nullptr;
+    if (cfg->budget_bytes <= 0 || cfg->streams < 1 || cfg->streams > 16 || cfg->max_batch < 0 ||
+        cfg->max_wait_us < 0)
+        return TDCT_EINVAL;
+    tdct_server* s = new (std::nothrow) tdct_server();
+    if (!s) return TDCT_ENOMEM;
+    s->cfg = *cfg;
+    if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
+    if (!s->cfg.tune.waves_per_group) s->cfg.tune.waves_per_group = 4;
+    if (!s->cfg.tune.groups_per_cu) s->cfg.tune.groups_per_cu = 8;
+    if (!s->cfg.tune.tile_waves) s->cfg.tune.tile_waves = 1;
+    s->fake = cfg->fake_device_us > 0;
+    s->t0 = Clock::now();
+    s->arena = new Arena(cfg->budget_bytes);
+    s->slots.resize((size_t)cfg->streams);
+    if (s->fake) {
+        s->arena_base = (char*)malloc((size_t)cfg->budget_bytes);
+        if (!s->arena_base) {
+            delete s->arena;
+            delete s;
+            return TDCT_ENOMEM;
+        }
+    } else {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipMalloc((void**)&s->arena_base, (size_t)cfg->budget_bytes);
+        for (Slot& sl : s->slots) {
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            set_error("server create", e);
+            for (Slot& sl : s->slots) {
+                if (sl.done) hipEventDestroy(sl.done);
+                if (sl.stream) hipStreamDestroy(sl.stream);
+            }
+            if (s->arena_base) hipFree(s->arena_base);
+            delete s->arena;
+            delete s;
+            return e == hipErrorOutOfMemory ? TDCT_ENOMEM : TDCT_EDEVICE;
+        }
+    }
+    s->worker = std::thread(scheduler, s);
+    *out = s;
+    return TDCT_OK;
+}
+
+static int submit_locked(tdct_server* s, const tdct_request* req, bool release_on_done,
+                         uint64_t* ticket) {
+    const int64_t ob = output_bytes(*req);
+    if (Arena::round(ob) > s->arena->size()) {
+        s->st.rejected++;
+        return TDCT_ENOMEM;
+    }
+    const uint64_t t = s->next_ticket++;
+    Req& q = s->reqs[t];
+    q.r = *req;
+    q.out_bytes = ob;
+    q.submit_us = s->now_us();
+    q.release_on_done = release_on_done;
+    s->waiting.push_back(t);
+    s->in_flight++;
+    s->st.submitted++;
+    *ticket = t;
+    return TDCT_OK;
+}
+
+int tdct_server_submit(tdct_server* s, const tdct_request* req, uint64_t* ticket) {
+    if (!s || !req || !ticket) return TDCT_EINVAL;
+    int st = validate_request(*req);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return TDCT_EBUSY;
+        st = submit_locked(s, req, false, ticket);
+    }
+    if (st == TDCT_OK) s->wake.notify_one();
+    return st;
+}
+
+static void fill_result(const tdct_server* s, const Req& q, tdct_result* out) {
+    out->status = q.status;
+    out->batch_size = q.batch_size;
+    out->output = (q.status == TDCT_OK && q.arena_off >= 0) ? s->arena_base + q.arena_off : nullptr;
+    out->output_bytes = q.out_bytes;
+    out->submit_us = q.submit_us;
+    out->done_us = q.done_us;
+}
+
+int tdct_server_poll(tdct_server* s, uint64_t ticket, tdct_result* out) {
+    if (!s || !out) return TDCT_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return TDCT_ENOTFOUND;
+    fill_result(s, it->second, out);
+    return TDCT_OK;
+}
+
+int tdct_server_wait(tdct_server* s, uint64_t ticket, tdct_result* out) {
+    if (!s || !out) return TDCT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return TDCT_ENOTFOUND;
+        if (it->second.status != TDCT_EBUSY) {
+            fill_result(s, it->second, out);
+            return TDCT_OK;
+        }
+        s->done.wait(lk);
+    }
+}
+
+int tdct_server_release(tdct_server* s, uint64_t ticket) {
+    if (!s) return TDCT_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return TDCT_ENOTFOUND;
+        if (it->second.status == TDCT_EBUSY) return TDCT_EBUSY;
+        if (it->second.arena_off >= 0) s->arena->release(it->second.arena_off, it->second.out_bytes);
+        s->reqs.erase(it);
+    }
+    s->wake.notify_one();
+    return TDCT_OK;
+}
+
+int tdct_server_drain(tdct_server* s) {
+    if (!s) return TDCT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (s->in_flight > 0) s->done.wait(lk);
+    return TDCT_OK;
+}
+
+int tdct_server_stats(tdct_server* s, tdct_stats* out) {
+    if (!s || !out) return TDCT_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    out->batches = s->batches;
+    out->arena_bytes_in_use = s->arena->used();
+    out->arena_high_water = s->arena->high();
+    out->mean_batch = s->batches ? (double)s->batch_reqs / (double)s->batches : 0.0;
+    if (!s->lat.empty()) {
+        std::vector<double> v = s->lat;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            size_t k = (size_t)(p * (double)(v.size() - 1) + 0.5);
+            return v[std::min(k, v.size() - 1)];
+        };
+        out->p50_us = pct(0.50);
+        out->p99_us = pct(0.99);
+        out->p999_us = pct(0.999);
+        double sum = 0;
+        for (double x : v) sum += x;
+        out->mean_us = sum / (double)v.size();
+    }
+    return TDCT_OK;
+}
+
+void tdct_server_destroy(tdct_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->wake.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    if (s->fake) {
+        free(s->arena_base);
+    } else {
+        for (Slot& sl : s->slots) {
+            if (sl.stream) hipStreamSynchronize(sl.stream);
+            if (sl.done) hipEventDestroy(sl.done);
+            if (sl.stream) hipStreamDestroy(sl.stream);
+            if (sl.dev) hipFree(sl.dev);
+            if (sl.pinned) hipHostFree(sl.pinned);
+        }
+        if (s->arena_base) hipFree(s->arena_base);
+    }
+    delete s->arena;
+    delete s;
+}
+
+int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us, int32_t n,
+                       int32_t keep_outputs, uint64_t* tickets_out, double* latency_us,
+                       int32_t* status) {
+    if (!s || n < 0 || (n > 0 && (!reqs || !arrival_us))) return TDCT_EINVAL;
+    for (int32_t k = 0; k < n; ++k) {
+        int st = validate_request(reqs[k]);
+        if (st) return st;
+    }
+    std::vector<uint64_t> tk((size_t)n, 0);
+    std::vector<int32_t> sub((size_t)n, TDCT_OK);
+    const Clock::time_point start = Clock::now();
+    for (int32_t k = 0; k < n; ++k) {
+        const auto due = start + std::chrono::duration_cast<Clock::duration>(
+                                     std::chrono::duration<double, std::micro>(arrival_us[k]));
+        // Sleep most of the gap, spin the last stretch for an accurate arrival.
+        while (true) {
+            const auto left = due - Clock::now();
+            if (left <= Clock::duration::zero()) break;
+            if (left > std::chrono::microseconds(200))
+                std::this_thread::sleep_for(left - std::chrono::microseconds(100));
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            sub[k] = submit_locked(s, &reqs[k], !keep_outputs, &tk[k]);
+        }
+        s->wake.notify_one();
+    }
+    tdct_server_drain(s);
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int32_t k = 0; k < n; ++k) {
+        if (tickets_out) tickets_out[k] = tk[k];
+        auto it = s->reqs.find(tk[k]);
+        const bool ok = sub[k] == TDCT_OK && it != s->reqs.end();
+        if (latency_us) latency_us[k] = ok ? it->second.done_us - it->second.submit_us : -1.0;
+        if (status) status[k] = ok ? it->second.status : sub[k];
+        if (ok && !keep_outputs) s->reqs.erase(it);
+    }
+    return TDCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point that
+include/tdct.h declares, reports argument errors before touching a device,
+and its server logic (admission under a budget, FIFO order, batching,
+failure handling, drain) runs against the fake device."""
+import ctypes
+import os
+import re
+import time
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "tdct.h")
+
+
+@pytest.fixture(scope="module")
+def tdct():
+    import paper_1702_00817_amd as m
+    return m
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdct_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol(tdct):
+    names = _declared()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(tdct.lib(), n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_the_abi(tdct):
+    skip = {"tdct_plan_free", "tdct_server_destroy"}
+    for n in _declared():
+        assert hasattr(tdct, n) or n in skip, n
+
+
+def test_strerror_covers_every_status(tdct):
+    for st in range(0, -8, -1):
+        assert tdct.tdct_strerror(st) != "unknown status"
+    assert tdct.tdct_strerror(-99) == "unknown status"
+
+
+def test_argument_errors_need_no_device(tdct):
+    L = tdct.lib()
+    q = tdct.qtable(np.ones(64))
+    fake = 0x10000  # never dereferenced: validation fails first
+    r = ctypes.byref
+    assert L.tdct_quantise(fake, 8, 7, 8, r(q), 64, fake, None) == tdct.TDCT_EDIM
+    assert L.tdct_quantise(fake, 8, 8, 65544, r(q), 64, fake, None) == tdct.TDCT_EDIM
+    assert L.tdct_forward(None, 8, 8, 8, fake, None) == tdct.TDCT_EINVAL
+    assert L.tdct_inverse(fake + 4, r(q), 8, 8, fake, 8, None) == tdct.TDCT_EINVAL
+    assert L.tdct_roundtrip(fake, 8, 8, 8, r(q), 64, fake + 8, fake, 8, None) == tdct.TDCT_EINVAL
+    bad = tdct.qtable(np.ones(64))
+    bad.q[63] = 4096
+    assert L.tdct_quantise_i8_zigzag(fake, 8, 8, 8, r(bad), fake, None) == tdct.TDCT_EQTAB
+    assert L.tdct_sse(fake, 8, fake, 8, 8, 8, None, None) == tdct.TDCT_EINVAL
+    d = tdct.image_desc(tdct.OP_ENCODE, 16, 16, qtab=3, keep=64, src=fake, src_stride=16, coef=fake)
+    h = ctypes.c_void_p()
+    qa = (tdct.tdct_qtable * 1)(q)
+    assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, None, r(h)) == tdct.TDCT_EINVAL
+    d.qtab, d.keep = 0, 0
+    assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, None, r(h)) == tdct.TDCT_EINVAL
+    d.keep, d.op = 64, 9
+    assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, None, r(h)) == tdct.TDCT_EINVAL
+    t = tdct.tdct_tune(3, 1, 1, 0)
+    d.op = tdct.OP_ENCODE
+    assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, r(t), r(h)) == tdct.TDCT_EINVAL
+
+
+# ---- server logic on the fake device ----------------------------------------
+
+def _req(tdct, op, w, h, keep=64):
+    return tdct.request(op, w, h, 0x1000, np.ones(64), keep=keep)
+
+
+def test_fake_server_completes_everything_and_counts(tdct):
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 24, streams=2, max_batch=4, fake_device_us=200))
+    try:
+        tickets = [tdct.tdct_server_submit(s, _req(tdct, k % 2, 64, 32)) for k in range(20)]
+        tdct.tdct_server_drain(s)
+        for t in tickets:
+            r = tdct.tdct_server_poll(s, t)
+            assert r.status == tdct.TDCT_OK and r.output and r.done_us >= r.submit_us
+            assert 1 <= r.batch_size <= 4
+        st = tdct.tdct_server_stats(s)
+        assert st["completed"] == 20 and st["failed"] == 0 and st["batches"] >= 5
+        assert st["pixels_done"] == 20 * 64 * 32
+        assert st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"]
+        for t in tickets:
+            tdct.tdct_server_release(s, t)
+        assert tdct.tdct_server_stats(s)["arena_bytes_in_use"] == 0
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_poll(s, tickets[0])
+        assert e.value.status == tdct.TDCT_ENOTFOUND
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_server_admission_never_exceeds_budget(tdct):
+    budget = 3 * 64 * 64 * 2  # room for three encode outputs of 64 x 64
+    s = tdct.tdct_server_create(tdct.server_cfg(budget, streams=4, max_batch=8, fake_device_us=300))
+    try:
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 128, 128))
+        assert e.value.status == tdct.TDCT_ENOMEM
+        tickets = [tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 64, 64)) for _ in range(9)]
+        done = []
+        while len(done) < 9:
+            for t in tickets:
+                if t in done:
+                    continue
+                r = tdct.tdct_server_poll(s, t)
+                if r.status == tdct.TDCT_OK:
+                    done.append(t)
+                    tdct.tdct_server_release(s, t)
+            assert tdct.tdct_server_stats(s)["arena_high_water"] <= budget
+            time.sleep(0.0005)
+        # FIFO: completion order follows submission order in groups of three
+        assert done[:3] == sorted(done[:3]) and max(done[:3]) < min(done[3:])
+        st = tdct.tdct_server_stats(s)
+        assert st["arena_high_water"] <= budget and st["rejected"] == 1
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_server_failed_batches_do_not_stop_service(tdct):
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 22, streams=1, max_batch=1, fake_device_us=100,
+                                                fake_fail_every=3))
+    try:
+        tickets = [tdct.tdct_server_submit(s, _req(tdct, tdct.OP_DECODE, 32, 32)) for _ in range(9)]
+        tdct.tdct_server_drain(s)
+        status = [tdct.tdct_server_poll(s, t).status for t in tickets]
+        assert status.count(tdct.TDCT_EDEVICE) == 3 and status.count(tdct.TDCT_OK) == 6
+        st = tdct.tdct_server_stats(s)
+        assert st["failed"] == 3 and st["completed"] == 6
+        # failed requests gave their memory back
+        for t, stt in zip(tickets, status):
+            tdct.tdct_server_release(s, t)
+        assert tdct.tdct_server_stats(s)["arena_bytes_in_use"] == 0
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_server_batches_requests_that_arrive_together(tdct):
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 26, streams=1, max_batch=16, max_wait_us=20000,
+                                                fake_device_us=100))
+    try:
+        tickets = [tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 32, 32)) for _ in range(16)]
+        tdct.tdct_server_drain(s)
+        sizes = {tdct.tdct_server_poll(s, t).batch_size for t in tickets}
+        assert sizes == {16}
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_server_replay_and_shutdown_with_work_in_flight(tdct):
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 24, streams=2, max_batch=8, fake_device_us=500))
+    try:
+        reqs = [_req(tdct, k % 2, 32, 64) for k in range(50)]
+        arr = [k * 200.0 for k in range(50)]
+        tk, lat, st = tdct.tdct_server_replay(s, reqs, arr)
+        assert all(x == tdct.TDCT_OK for x in st) and min(lat) >= 500
+        assert tdct.tdct_server_stats(s)["arena_bytes_in_use"] == 0
+        for _ in range(10):
+            tdct.tdct_server_submit(s, _req(tdct, 0, 64, 64))
+    finally:
+        tdct.tdct_server_destroy(s)  # drains the ten in flight, then stops
+
+
+def test_server_rejects_bad_requests(tdct):
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 20, fake_device_us=10))
+    try:
+        for r in (tdct.request(5, 8, 8, 0x1000, np.ones(64)), tdct.request(0, 12, 8, 0x1000, np.ones(64)),
+                  tdct.request(0, 8, 8, None, np.ones(64)), tdct.request(1, 8, 8, 0x1008, np.ones(64)),
+                  tdct.request(0, 8, 8, 0x1000, np.zeros(64))):
+            with pytest.raises(tdct.TdctError):
+                tdct.tdct_server_submit(s, r)
+    finally:
+        tdct.tdct_server_destroy(s)

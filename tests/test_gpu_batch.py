@@ -1,0 +1,273 @@
+"""Batch form on the GPU: one persistent launch over many images of uneven
+sizes, its hipGraph replay, every launch shape the autotuner may pick, and
+one plain launch per image must all give the oracle's bytes. The full-size
+workloads (64 images of 4096 x 4096; 10,000 ragged images; 4:2:0 frames)
+run in the launch configuration the benchmark times and are checked on
+sampled blocks, each recomputed by the oracle from its own pixels."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import sync
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tdct():
+    import paper_1702_00817_amd as m
+    return m
+
+
+def _block(img, w, b):
+    nbx = w // 8
+    by, bx = divmod(int(b), nbx)
+    return np.ascontiguousarray(img[8 * by:8 * by + 8, 8 * bx:8 * bx + 8])
+
+
+class Ragged:
+    """A mixed batch: every op, uneven sizes (odd blocks per row, strips,
+    single blocks), strides wider than the image, several Q tables."""
+
+    def __init__(self, tdct, seed=5):
+        import torch
+        rng = np.random.default_rng(seed)
+        self.qtabs = [synth.qtable(1, s) for s in (1, 3, 8)] + [rng.integers(1, 4096, 64).astype(np.uint16)]
+        sizes = [(8, 8), (24, 16), (136, 72), (1024, 64), (8, 1024), (520, 48), (40, 40), (2048, 24)]
+        sizes += [(8 * int(a), 8 * int(b)) for a, b in rng.integers(1, 40, size=(24, 2))]
+        self.items = []
+        ops = [tdct.OP_ENCODE, tdct.OP_DECODE, tdct.OP_ROUNDTRIP, tdct.OP_ENCODE_I8ZZ, tdct.OP_FORWARD]
+        self.keep_alive = []
+        for k, (w, h) in enumerate(sizes):
+            op = ops[k % len(ops)]
+            stride = w + (8 * (k % 3)) + (3 if k % 7 == 3 else 0)
+            img = synth.plane(w, h, 500 + k, stride=stride)
+            qt = k % len(self.qtabs)
+            keep = [64, 10, 25, 1][k % 4]
+            nblk = (w // 8) * (h // 8)
+            it = dict(op=op, w=w, h=h, img=img, qt=qt, keep=keep, stride=stride, nblk=nblk)
+            it["src"] = torch.from_numpy(img).cuda()
+            if op == tdct.OP_DECODE:
+                qin = rng.integers(-2000, 2000, size=(nblk, 64)).astype(np.int16)
+                it["qin"] = qin
+                it["coef"] = torch.from_numpy(qin).cuda()
+            elif op in (tdct.OP_ENCODE, tdct.OP_ROUNDTRIP):
+                it["coef"] = torch.zeros((nblk, 64), dtype=torch.int16, device="cuda")
+            elif op == tdct.OP_ENCODE_I8ZZ:
+                it["coef"] = torch.zeros((nblk, 64), dtype=torch.int8, device="cuda")
+            else:
+                it["coef"] = torch.zeros((nblk, 64), dtype=torch.int32, device="cuda")
+            it["dst"] = torch.zeros((h, stride), dtype=torch.uint8, device="cuda")
+            self.items.append(it)
+        self.descs = []
+        for it in self.items:
+            self.descs.append(tdct.image_desc(it["op"], it["w"], it["h"], qtab=it["qt"], keep=it["keep"],
+                                              src=it["src"], src_stride=it["stride"], coef=it["coef"],
+                                              dst=it["dst"], dst_stride=it["stride"]))
+
+    def clear(self):
+        for it in self.items:
+            if it["op"] != 1:
+                it["coef"].zero_()
+            it["dst"].zero_()
+
+    def check(self, tdct):
+        sync()
+        for it in self.items:
+            op, w, h, Q = it["op"], it["w"], it["h"], self.qtabs[it["qt"]]
+            img = it["img"]
+            if op == tdct.OP_ENCODE:
+                assert np.array_equal(it["coef"].cpu().numpy(), O.quantise(img, Q, it["keep"], w=w))
+            elif op == tdct.OP_DECODE:
+                assert np.array_equal(it["dst"].cpu().numpy()[:, :w], O.inverse(it["qin"], Q, w, h))
+            elif op == tdct.OP_ROUNDTRIP:
+                q = O.quantise(img, Q, it["keep"], w=w)
+                assert np.array_equal(it["coef"].cpu().numpy(), q)
+                assert np.array_equal(it["dst"].cpu().numpy()[:, :w], O.inverse(q, Q, w, h))
+            elif op == tdct.OP_ENCODE_I8ZZ:
+                assert np.array_equal(it["coef"].cpu().numpy(), O.quantise_i8_zigzag(img, Q, w=w))
+            else:
+                assert np.array_equal(it["coef"].cpu().numpy(), O.forward(img, w=w))
+
+
+def test_ragged_mixed_batch_one_launch(tdct):
+    R = Ragged(tdct)
+    plan = tdct.tdct_batch_plan(R.descs, R.qtabs)
+    try:
+        info = tdct.tdct_plan_info_get(plan)
+        assert info["images"] == len(R.items)
+        assert info["blocks"] == sum(it["nblk"] for it in R.items)
+        tdct.tdct_batch_run(plan)
+        R.check(tdct)
+    finally:
+        tdct.tdct_plan_free(plan)
+
+
+def test_graph_replays_equal_direct_launch(tdct):
+    R = Ragged(tdct, seed=6)
+    plan = tdct.tdct_batch_plan(R.descs, R.qtabs)
+    try:
+        for _ in range(3):
+            R.clear()
+            sync()
+            tdct.tdct_batch_graph(plan)
+            R.check(tdct)
+    finally:
+        tdct.tdct_plan_free(plan)
+
+
+@pytest.mark.parametrize("tune", [dict(waves_per_group=1, groups_per_cu=1, tile_waves=1),
+                                  dict(waves_per_group=2, groups_per_cu=3, tile_waves=2),
+                                  dict(waves_per_group=8, groups_per_cu=4, tile_waves=4),
+                                  dict(waves_per_group=16, groups_per_cu=2, tile_waves=1)])
+def test_every_launch_shape_gives_same_bytes(tdct, tune):
+    R = Ragged(tdct, seed=7)
+    plan = tdct.tdct_batch_plan(R.descs, R.qtabs, tune=tune)
+    try:
+        tdct.tdct_batch_run(plan)
+        R.check(tdct)
+    finally:
+        tdct.tdct_plan_free(plan)
+
+
+def test_autotuner_result_and_per_image_launches(tdct):
+    R = Ragged(tdct, seed=8)
+    plan = tdct.tdct_batch_plan(R.descs, R.qtabs)
+    try:
+        best = tdct.tdct_autotune(plan, reps=1)
+        assert best["waves_per_group"] in (1, 2, 4, 8)
+        R.clear()
+        tdct.tdct_batch_run(plan)
+        R.check(tdct)
+        R.clear()
+        tdct.tdct_run_per_image(R.descs, R.qtabs)
+        R.check(tdct)
+    finally:
+        tdct.tdct_plan_free(plan)
+
+
+# ---- full-size workloads ------------------------------------------------------
+
+def test_large_batch_64_images_4096(tdct):
+    """64 images of 4096 x 4096, per-image Q = 1 + s (i + j): one persistent
+    encode launch and one decode launch, as timed by the benchmark."""
+    import torch
+    sizes, seeds, qs = synth.large_batch_spec()
+    n, side = len(sizes), sizes[0][0]
+    buf, off, strides = synth.batch(sizes, seeds)
+    src = torch.from_numpy(buf).cuda()
+    nblk = (side // 8) ** 2
+    coef = torch.empty((n, nblk, 64), dtype=torch.int16, device="cuda")
+    dst = torch.empty((n, side, side), dtype=torch.uint8, device="cuda")
+    base = src.data_ptr()
+    enc = [tdct.image_desc(tdct.OP_ENCODE, side, side, qtab=i, keep=64, src=base + int(off[i]),
+                           src_stride=side, coef=coef[i]) for i in range(n)]
+    dec = [tdct.image_desc(tdct.OP_DECODE, side, side, qtab=i, coef=coef[i], dst=dst[i],
+                           dst_stride=side) for i in range(n)]
+    pe, pd = tdct.tdct_batch_plan(enc, qs), tdct.tdct_batch_plan(dec, qs)
+    try:
+        tdct.tdct_batch_run(pe)
+        tdct.tdct_batch_run(pd)
+        sync()
+        rng = np.random.default_rng(99)
+        for i in list(range(0, n, 7)) + [n - 1]:
+            img = synth.batch_view(buf, off, strides, sizes, i)
+            blocks = np.concatenate([[0, nblk - 1, 511, 512], rng.integers(0, nblk, 60)])
+            qi = coef[i].cpu().numpy()
+            di = dst[i].cpu().numpy()
+            for b in blocks:
+                blk = _block(img, side, b)
+                q_ref, rec_ref = O.roundtrip(blk, qs[i])
+                assert np.array_equal(qi[b], q_ref[0]), (i, b)
+                assert np.array_equal(_block(di, side, b), rec_ref), (i, b)
+        # any-size property: decoding an encoding at Q = 1 + s (i + j) never
+        # moves a pixel of these fields by more than the quantiser allows
+        assert int((dst.float() - src[:n * side * side].view(n, side, side).float()).abs().max()) < 128
+    finally:
+        tdct.tdct_plan_free(pe)
+        tdct.tdct_plan_free(pd)
+
+
+def test_ragged_10000_images_one_persistent_launch(tdct):
+    """10,000 images with log-uniform sides in [64, 2048]: full encode +
+    decode round trip with coefficients, one launch from the block-offset
+    table, replayed through a graph, against one plain launch per image."""
+    import torch
+    sizes, seeds, qs = synth.ragged_batch_spec()
+    n = len(sizes)
+    buf, off, strides = synth.batch(sizes, seeds)
+    src = torch.from_numpy(buf).cuda()
+    nblk = np.array([(w // 8) * (h // 8) for w, h in sizes], np.int64)
+    boff = np.concatenate([[0], np.cumsum(nblk)])
+    coef = torch.empty((int(boff[-1]), 64), dtype=torch.int16, device="cuda")
+    dst = torch.zeros(buf.size, dtype=torch.uint8, device="cuda")  # gaps between images stay 0
+    base, cb, db = src.data_ptr(), coef.data_ptr(), dst.data_ptr()
+    descs = [tdct.image_desc(tdct.OP_ROUNDTRIP, w, h, qtab=i, keep=64, src=base + int(off[i]),
+                             src_stride=w, coef=cb + 128 * int(boff[i]), dst=db + int(off[i]),
+                             dst_stride=w) for i, (w, h) in enumerate(sizes)]
+    plan = tdct.tdct_batch_plan(descs, qs)
+    try:
+        tdct.tdct_batch_graph(plan)
+        tdct.tdct_batch_graph(plan)
+        sync()
+        rng = np.random.default_rng(3)
+        dh = dst.cpu().numpy()
+        ch = coef.cpu().numpy()
+        for i in rng.choice(n, 400, replace=False).tolist() + [0, n - 1]:
+            w, h = sizes[i]
+            img = synth.batch_view(buf, off, strides, sizes, i)
+            rec = synth.batch_view(dh, off, strides, sizes, i)
+            for b in [0, int(nblk[i]) - 1, int(rng.integers(0, nblk[i]))]:
+                q_ref, rec_ref = O.roundtrip(_block(img, w, b), qs[i])
+                assert np.array_equal(ch[boff[i] + b], q_ref[0]), (i, b)
+                assert np.array_equal(_block(rec, w, b), rec_ref), (i, b)
+        for i in range(20):  # whole images too
+            w, h = sizes[i]
+            img = np.ascontiguousarray(synth.batch_view(buf, off, strides, sizes, i))
+            q_ref, rec_ref = O.roundtrip(img, qs[i])
+            assert np.array_equal(ch[boff[i]:boff[i + 1]], q_ref)
+            assert np.array_equal(synth.batch_view(dh, off, strides, sizes, i), rec_ref)
+        # one plain launch per image writes the very same bytes
+        coef2 = torch.empty_like(coef)
+        dst2 = torch.zeros_like(dst)
+        d2 = [tdct.image_desc(tdct.OP_ROUNDTRIP, w, h, qtab=i, keep=64, src=base + int(off[i]),
+                              src_stride=w, coef=coef2.data_ptr() + 128 * int(boff[i]),
+                              dst=dst2.data_ptr() + int(off[i]), dst_stride=w)
+              for i, (w, h) in enumerate(sizes)]
+        tdct.tdct_run_per_image(d2, qs)
+        sync()
+        assert torch.equal(coef, coef2) and torch.equal(dst, dst2)
+    finally:
+        tdct.tdct_plan_free(plan)
+
+
+def test_video_420_frames_int8_zigzag(tdct):
+    """3840 x 2160 4:2:0 frames (first, last and seeded frames of the
+    256-frame sequence) in one batched launch with luma/chroma Q tables."""
+    import torch
+    v = synth.Video420()
+    rng = np.random.default_rng(4)
+    frames = sorted(set([0, v.frames - 1] + rng.integers(1, v.frames - 1, 6).tolist()))
+    planes, descs, qtabs, outs = [], [], [], []
+    for k, f in enumerate(frames):
+        Y, Cb, Cr = v.frame(f)
+        qy, qc = v.qtables(f)
+        qtabs += [qy, qc]
+        for p, (pl, qi) in enumerate([(Y, 2 * k), (Cb, 2 * k + 1), (Cr, 2 * k + 1)]):
+            h, w = pl.shape
+            d = torch.from_numpy(pl).cuda()
+            o = torch.empty(((w // 8) * (h // 8), 64), dtype=torch.int8, device="cuda")
+            planes.append((pl, qi))
+            outs.append(o)
+            descs.append(tdct.image_desc(tdct.OP_ENCODE_I8ZZ, w, h, qtab=qi, src=d, src_stride=w, coef=o))
+            outs.append(d)
+    plan = tdct.tdct_batch_plan(descs, qtabs)
+    try:
+        tdct.tdct_batch_run(plan)
+        sync()
+        for j, (pl, qi) in enumerate(planes):
+            got = outs[2 * j].cpu().numpy()
+            assert np.array_equal(got, O.quantise_i8_zigzag(pl, qtabs[qi], threads=8)), j
+    finally:
+        tdct.tdct_plan_free(plan)
