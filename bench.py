@@ -180,7 +180,7 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
     return {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
             "graph_gpx_s": round(px / graph_s / 1e9, 2), "graph_ms": round(graph_s * 1e3, 3),
             "per_image_gpx_s": round(px / per_s / 1e9, 2), "per_image_ms": round(per_s * 1e3, 3),
-            "speedup": round(per_s / graph_s, 2), "bytes_per_px": 6}
+            "speedup": round(per_s / graph_s, 2), "bytes_per_px": 4}
 
 
 def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
@@ -250,6 +250,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
+    ap.add_argument("--tune", default="",
+                    help="fixed launch shapes instead of autotuning: "
+                         "'WPG,GPC,TW:WPG,GPC,TW' for the encoder and the decoder")
     ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
@@ -269,21 +272,34 @@ def main():
     torch.cuda.set_stream(stream)
 
     if args.copy_only:
+        # A plain device copy of a known size: the calibration kernel for the
+        # HBM counters and the practical copy ceiling of the part.
         n = args.copy_only << 20
         a = torch.ones(n, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
-        for _ in range(5):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        b.copy_(a)
+        for k in range(5):
+            ev[k].record(stream)
             b.copy_(a)
+        ev[5].record(stream)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": n, "launches": 5}))
+        ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(5))[2]
+        print(json.dumps({"copy_bytes": n, "launches": 6, "median_ms": round(ms, 4),
+                          "copy_gbs": round(2 * n / (ms / 1e3) / 1e9, 1)}))
         return
 
     W = make_large_batch(tdct, torch, args.images, args.side)
-    pe = tdct.tdct_batch_plan(W["enc"], W["qs"])
-    pd = tdct.tdct_batch_plan(W["dec"], W["qs"])
+    fixed = [None, None]
+    if args.tune:
+        for k, part in enumerate(args.tune.split(":")):
+            a, b, c = (int(x) for x in part.split(","))
+            fixed[k] = dict(waves_per_group=a, groups_per_cu=b, tile_waves=c)
+    pe = tdct.tdct_batch_plan(W["enc"], W["qs"], tune=fixed[0])
+    pd = tdct.tdct_batch_plan(W["dec"], W["qs"], tune=fixed[1])
     try:
-        tune_e = tune_d = None
-        if not args.no_tune:
+        tune_e, tune_d = fixed
+        if not args.no_tune and not args.tune:
             tune_e = tdct.tdct_autotune(pe, stream, reps=3)
             tune_d = tdct.tdct_autotune(pd, stream, reps=3)
             log("autotune: encode %s decode %s" % (tune_e, tune_d))

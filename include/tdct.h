@@ -136,7 +136,7 @@ typedef struct {
 
 /* Launch shape of the persistent kernel. Zero fields take defaults. */
 typedef struct {
-    int32_t waves_per_group; /* 1, 2, 4, 8 or 16 (64-lane waves per workgroup) */
+    int32_t waves_per_group; /* 1, 2, 4 or 8 (64-lane waves per workgroup) */
     int32_t groups_per_cu;   /* resident workgroups per compute unit; grid = CUs * this */
     int32_t tile_waves;      /* consecutive wave-tiles one wave takes per step (1, 2, 4) */
     int32_t reserved;

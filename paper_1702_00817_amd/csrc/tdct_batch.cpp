@@ -34,6 +34,7 @@ struct tdct_plan {
     ImgDesc* imgs_d = nullptr;
     QConst* qcs_d = nullptr;
     tdct_tune tune{};
+    int ops = 0;  // bit i set when some image uses op i
     int num_cus = 0;
     int64_t pixels = 0;
     hipGraphExec_t exec = nullptr;
@@ -59,8 +60,8 @@ int normalise_tune(const tdct_tune* in, tdct_tune* out) {
         if (in->tile_waves) t.tile_waves = in->tile_waves;
     }
     const int w = t.waves_per_group;
-    if (!(w == 1 || w == 2 || w == 4 || w == 8 || w == 16)) return TDCT_EINVAL;
-    if (t.groups_per_cu < 1 || t.groups_per_cu > 64) return TDCT_EINVAL;
+    if (!(w == 1 || w == 2 || w == 4 || w == 8)) return TDCT_EINVAL;
+    if (t.groups_per_cu < 1 || t.groups_per_cu > 4096) return TDCT_EINVAL;
     if (!(t.tile_waves == 1 || t.tile_waves == 2 || t.tile_waves == 4)) return TDCT_EINVAL;
     *out = t;
     return TDCT_OK;
@@ -103,8 +104,8 @@ void free_graph(tdct_plan* p) {
 }
 
 int run(tdct_plan* p, hipStream_t s) {
-    return launch_batch(p->tiles_d, p->imgs_d, p->qcs_d, (uint32_t)p->tiles.size(), p->tune,
-                        p->num_cus, s);
+    return launch_batch(p->tiles_d, p->imgs_d, p->qcs_d, (uint32_t)p->tiles.size(), p->ops,
+                        p->tune, p->num_cus, s);
 }
 
 }  // namespace
@@ -158,6 +159,7 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
         fill_desc(im.op, im.src, im.src_stride, im.w, im.h, im.coef, im.dst, im.dst_stride, qi,
                   im.op == TDCT_OP_ROUNDTRIP && im.coef != nullptr, &p->imgs[i]);
         p->blk_off[i + 1] = p->blk_off[i] + p->imgs[i].nblk;
+        p->ops |= 1 << im.op;
         p->pixels += (int64_t)im.w * im.h;
     }
     if (p->qcs.empty()) {
@@ -274,13 +276,16 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
     tdct_tune winner = saved;
     float best_ms = 1e30f;
     int st = TDCT_OK;
+    // Launch shapes: persistent grids of 1..16 resident waves per CU, and a
+    // full grid (every wave takes tile_waves tiles and exits).
     const int wpgs[] = {1, 2, 4, 8};
-    const int gpcs[] = {1, 2, 4, 8, 16, 32};
+    const int gpcs[] = {1, 2, 4, 8, 16, 4096};
     const int tws[] = {1, 2};
     for (int wpg : wpgs)
         for (int gpc : gpcs)
             for (int tw : tws) {
-                if (wpg * gpc > 32) continue;  // at most 32 waves per CU are resident
+                if (gpc < 4096 && wpg * gpc > 32) continue;  // at most 32 waves per CU are resident
+                if (batch_lds_bytes(p->ops, wpg) > 160 * 1024) continue;
                 tdct_tune t{};
                 t.waves_per_group = wpg;
                 t.groups_per_cu = gpc;

@@ -151,7 +151,6 @@ enum : int32_t { OP_ENCODE = 0, OP_DECODE = 1, OP_ROUNDTRIP = 2, OP_ENCODE_I8ZZ 
 // Flags describing which load/store widths an image allows.
 enum : int32_t {
     F_SRC8 = 1,    // src and src_stride 8-byte aligned
-    F_SRC16 = 2,   // src, src_stride 16-byte aligned and an even number of blocks per row
     F_DST8 = 4,    // dst and dst_stride 8-byte aligned
     F_COEF = 8     // coefficients are written (ROUNDTRIP)
 };

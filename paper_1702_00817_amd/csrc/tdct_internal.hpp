@@ -19,7 +19,10 @@ int image_flags(const ImgDesc& d);
 int fill_desc(int op, const uint8_t* src, int64_t src_stride, int32_t w, int32_t h, void* coef,
               uint8_t* dst, int64_t dst_stride, int32_t qidx, bool write_coef, ImgDesc* d);
 int launch_plain_op(int op, const ImgDesc& d, const QConst& qc, hipStream_t stream);
+// ops: bit i set when op i occurs in the tiles (selects the kernel instance).
 int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
-                 const tdct_tune& tune, int num_cus, hipStream_t stream);
+                 int ops, const tdct_tune& tune, int num_cus, hipStream_t stream);
+// LDS bytes per workgroup of the batch kernel for an op set and launch shape.
+uint32_t batch_lds_bytes(int ops, int waves_per_group);
 
 }  // namespace tdct

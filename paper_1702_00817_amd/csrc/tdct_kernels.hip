@@ -26,9 +26,29 @@
 namespace tdct {
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
-__device__ __forceinline__ uint32_t as_u32(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// Streaming accesses: every byte is touched once, so loads and stores carry
+// the non-temporal hint and do not displace other data in L2 / MALL.
+__device__ __forceinline__ v4u ld_nt4(const void* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+}
+__device__ __forceinline__ v2u ld_nt2(const void* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const v2u*>(p));
+}
+__device__ __forceinline__ void st_nt4(void* p, v4u v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(p));
+}
+__device__ __forceinline__ void st_nt2(void* p, v2u v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<v2u*>(p));
+}
+
+// LDS writes of this wave complete before its following LDS reads (and the
+// compiler keeps LDS accesses on their side of this point).
+__device__ __forceinline__ void lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // Pack two int32 values (known to fit 16 bits) into one dword, low first.
 __device__ __forceinline__ uint32_t pack16(int lo, int hi) {
@@ -42,22 +62,76 @@ __device__ __forceinline__ uint32_t pack8(int b0, int b1, int b2, int b3) {
     return lo | hi;
 }
 
-// ---- pixel loads ---------------------------------------------------------
+// ---- coefficient-side staging through LDS ------------------------------------
+//
+// Every lane owns whole blocks, so the coefficients of one of its blocks form
+// CPL consecutive 16-byte chunks (CPL = 8: an int16 block; CPL = 4: an int8
+// block) of the contiguous run that 64 consecutive blocks occupy. Direct
+// stores would make every instruction touch 64 chunks CPL * 16 bytes apart.
+// Instead the wave writes its chunks to its own LDS slice and reads them back
+// so that instruction k moves chunks 64k .. 64k + 63, i.e. 1 KB of
+// consecutive bytes (and the reverse for the decoder's loads). Chunk m of
+// lane L sits at slot CPL * L + (m ^ swz(L)); the XOR puts any 8 and any 16
+// consecutive lanes of both access patterns on distinct 16-byte bank groups,
+// whether the LDS has 32 or 64 four-byte banks.
+template <int CPL>
+__device__ __forceinline__ uint32_t swz(uint32_t L) {
+    return CPL == 8 ? ((L ^ (L >> 3)) & 7u) : (((L >> 1) ^ (L >> 2)) & 3u);
+}
 
-// Rows of block a (A[r][0..1]) and block b (B[r][0..1]) as little-endian
-// dwords. `pair16`: b is a's right neighbour and one 16-byte load per row
-// fetches both.
-struct PixRows {
-    uint32_t A[8][2];
-    uint32_t B[8][2];
-};
+// Stores the run of 64 * CPL chunks at dst (only its first nchunks) from
+// lane-owned chunks.
+template <int CPL>
+__device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint32_t nchunks,
+                                          v4u* dst, uint32_t lane) {
+#pragma unroll
+    for (int m = 0; m < CPL; ++m) wl[CPL * lane + ((uint32_t)m ^ swz<CPL>(lane))] = mine[m];
+    lds_fence();
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const uint32_t c = 64u * k + lane;
+        const uint32_t L = c / CPL, m = c % CPL;
+        const v4u v = wl[CPL * L + (m ^ swz<CPL>(L))];
+        if (c < nchunks) st_nt4(dst + c, v);
+    }
+    asm volatile("" ::: "memory");
+}
+
+// Loads the run of 512 chunks at src (only its first nchunks; the rest read
+// as zero) and hands every lane the 8 chunks of its own int16 block.
+__device__ __forceinline__ void stage_in(v4u* wl, const v4u* src, uint32_t nchunks, uint32_t lane,
+                                         v4u (&mine)[8]) {
+    v4u tmp[8];
+    if (nchunks == 512) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tmp[k] = ld_nt4(src + 64u * k + lane);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t c = 64u * k + lane;
+            tmp[k] = c < nchunks ? ld_nt4(src + c) : (v4u){0u, 0u, 0u, 0u};
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t c = 64u * k + lane;
+        const uint32_t L = c >> 3, m = c & 7u;
+        wl[8 * L + (m ^ swz<8>(L))] = tmp[k];
+    }
+    lds_fence();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) mine[m] = wl[8 * lane + ((uint32_t)m ^ swz<8>(lane))];
+    asm volatile("" ::: "memory");
+}
+
+// ---- pixel side ---------------------------------------------------------------
 
 __device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int flags,
                                            uint32_t (&R)[8][2]) {
     if (flags & F_SRC8) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            uint2 v = *reinterpret_cast<const uint2*>(p + r * stride);
+            const v2u v = ld_nt2(p + r * stride);
             R[r][0] = v.x;
             R[r][1] = v.y;
         }
@@ -77,8 +151,7 @@ __device__ __forceinline__ void store_rows8(uint8_t* p, int64_t stride, int flag
                                             const uint32_t (&R)[8][2]) {
     if (flags & F_DST8) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
-            *reinterpret_cast<uint2*>(p + r * stride) = make_uint2(R[r][0], R[r][1]);
+        for (int r = 0; r < 8; ++r) st_nt2(p + r * stride, (v2u){R[r][0], R[r][1]});
     } else {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -92,11 +165,10 @@ __device__ __forceinline__ void store_rows8(uint8_t* p, int64_t stride, int flag
     }
 }
 
-__device__ __forceinline__ const uint8_t* block_ptr(const uint8_t* base, int64_t stride,
-                                                    uint32_t nbx, uint32_t b) {
-    uint32_t by = b / nbx;
-    uint32_t bx = b - by * nbx;
-    return base + (int64_t)(8 * by) * stride + 8 * bx;
+__device__ __forceinline__ int64_t block_offset(int64_t stride, uint32_t nbx, uint32_t b) {
+    const uint32_t by = b / nbx;
+    const uint32_t bx = b - by * nbx;
+    return (int64_t)(8 * by) * stride + 8 * bx;
 }
 
 // ---- decoder core ----------------------------------------------------------
@@ -109,10 +181,9 @@ __device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC&
     int W[64];
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
-        int lo = (int)(short)(qp[k] & 0xffffu);
-        int hi = (int)qp[k] >> 16;
-        W[2 * k] = lo * qc.Q[2 * k];
-        W[2 * k + 1] = hi * qc.Q[2 * k + 1];
+        // |q| <= 2^15 and Q <= 4095 fit the 24-bit multiplier exactly.
+        W[2 * k] = __mul24((int)(short)(qp[k] & 0xffffu), qc.Q[2 * k]);
+        W[2 * k + 1] = __mul24((int)qp[k] >> 16, qc.Q[2 * k + 1]);
     }
     // +32 rounds floor((S + 32) / 64); +8192 = 64 * 128 undoes the level
     // shift. Column 0 of T^t is all ones, so adding both to W'_00 adds them
@@ -130,36 +201,36 @@ __device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC&
 }
 
 // ---- encoder tile ------------------------------------------------------------
+//
+// Lane l owns blocks first + l (a) and first + 64 + l (b) of the tile. The
+// rows of 64 consecutive blocks are contiguous, so each pixel load covers a
+// 512-byte run, and the coefficients of all a-blocks (then all b-blocks) are
+// one contiguous 8 KB run for the staged stores.
 
 template <int OP, class QC>
 __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
-                                         uint32_t count, int lane) {
-    const uint32_t la = 2u * (uint32_t)lane, lb = la + 1u;
-    const bool va = la < count, vb = lb < count;
-    if (!va) return;
+                                         uint32_t count, uint32_t lane, v4u* wl) {
+    const bool va = lane < count, vb = lane + 64u < count;
     const uint32_t nbx = (uint32_t)d.nbx;
-    const uint32_t ba = first + la, bb = first + lb;
+    const uint32_t ba = first + lane, bb = ba + 64u;
 
     uint32_t A[8][2], B[8][2];
-    const uint8_t* pa = block_ptr(d.src, d.src_stride, nbx, ba);
-    if (d.flags & F_SRC16) {
-        // b is a's right neighbour in the same row, 16-byte aligned.
+    if (count == (uint32_t)kEncTileBlocks && (d.flags & F_SRC8)) {
+        const uint8_t* pa = d.src + block_offset(d.src_stride, nbx, ba);
+        const uint8_t* pb = d.src + block_offset(d.src_stride, nbx, bb);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            uint4 v = *reinterpret_cast<const uint4*>(pa + r * d.src_stride);
-            A[r][0] = v.x;
-            A[r][1] = v.y;
-            B[r][0] = v.z;
-            B[r][1] = v.w;
+            const v2u x = ld_nt2(pa + r * d.src_stride), y = ld_nt2(pb + r * d.src_stride);
+            A[r][0] = x.x;
+            A[r][1] = x.y;
+            B[r][0] = y.x;
+            B[r][1] = y.y;
         }
     } else {
-        load_rows8(pa, d.src_stride, d.flags, A);
-        if (vb) {
-            load_rows8(block_ptr(d.src, d.src_stride, nbx, bb), d.src_stride, d.flags, B);
-        } else {
 #pragma unroll
-            for (int r = 0; r < 8; ++r) B[r][0] = B[r][1] = 0x80808080u;
-        }
+        for (int r = 0; r < 8; ++r) A[r][0] = A[r][1] = B[r][0] = B[r][1] = 0x80808080u;
+        if (va) load_rows8(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, A);
+        if (vb) load_rows8(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, B);
     }
 
     // Pixel (r, c) of both blocks as a packed (a, b) int16 pair.
@@ -176,45 +247,46 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
     fwd8x8(v);
     v[0] -= (s16x2){8192, 8192};
 
+    const uint32_t na = min(count, 64u), nb = count > 64u ? count - 64u : 0u;
     if constexpr (OP == OP_FORWARD) {
-        int32_t* oa = reinterpret_cast<int32_t*>(d.coef) + (int64_t)ba * 64;
+        if (va) {
+            int32_t* oa = reinterpret_cast<int32_t*>(d.coef) + (int64_t)ba * 64;
 #pragma unroll
-        for (int k = 0; k < 64; k += 4)
-            *reinterpret_cast<int4*>(oa + k) = make_int4(v[k].x, v[k + 1].x, v[k + 2].x, v[k + 3].x);
+            for (int k = 0; k < 64; k += 4)
+                st_nt4(oa + k, (v4u){(uint32_t)(int)v[k].x, (uint32_t)(int)v[k + 1].x,
+                                     (uint32_t)(int)v[k + 2].x, (uint32_t)(int)v[k + 3].x});
+        }
         if (vb) {
             int32_t* ob = reinterpret_cast<int32_t*>(d.coef) + (int64_t)bb * 64;
 #pragma unroll
             for (int k = 0; k < 64; k += 4)
-                *reinterpret_cast<int4*>(ob + k) =
-                    make_int4(v[k].y, v[k + 1].y, v[k + 2].y, v[k + 3].y);
+                st_nt4(ob + k, (v4u){(uint32_t)(int)v[k].y, (uint32_t)(int)v[k + 1].y,
+                                     (uint32_t)(int)v[k + 2].y, (uint32_t)(int)v[k + 3].y});
         }
-        return;
     } else if constexpr (OP == OP_ENCODE_I8ZZ) {
-        uint32_t qa[16], qb[16];
+        // int8, zigzag order: 64 bytes (4 chunks) per block.
+        v4u ma[4], mb[4];
 #pragma unroll
-        for (int n = 0; n < 64; n += 4) {
-            int a4[4], b4[4];
+        for (int n = 0; n < 64; n += 16) {
+            uint32_t wa[4], wb[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int k = kZigzag.order[n + t];
-                a4[t] = min(max(quant_f32(v[k].x, qc.r[k]), -128), 127) & 0xff;
-                b4[t] = min(max(quant_f32(v[k].y, qc.r[k]), -128), 127) & 0xff;
+            for (int g = 0; g < 4; ++g) {
+                int a4[4], b4[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = kZigzag.order[n + 4 * g + t];
+                    a4[t] = min(max(quant_f32(v[k].x, qc.r[k]), -128), 127) & 0xff;
+                    b4[t] = min(max(quant_f32(v[k].y, qc.r[k]), -128), 127) & 0xff;
+                }
+                wa[g] = pack8(a4[0], a4[1], a4[2], a4[3]);
+                wb[g] = pack8(b4[0], b4[1], b4[2], b4[3]);
             }
-            qa[n / 4] = pack8(a4[0], a4[1], a4[2], a4[3]);
-            qb[n / 4] = pack8(b4[0], b4[1], b4[2], b4[3]);
+            ma[n / 16] = (v4u){wa[0], wa[1], wa[2], wa[3]};
+            mb[n / 16] = (v4u){wb[0], wb[1], wb[2], wb[3]};
         }
-        int8_t* oa = reinterpret_cast<int8_t*>(d.coef) + (int64_t)ba * 64;
-#pragma unroll
-        for (int k = 0; k < 16; k += 4)
-            *reinterpret_cast<uint4*>(oa + 4 * k) = make_uint4(qa[k], qa[k + 1], qa[k + 2], qa[k + 3]);
-        if (vb) {
-            int8_t* ob = reinterpret_cast<int8_t*>(d.coef) + (int64_t)bb * 64;
-#pragma unroll
-            for (int k = 0; k < 16; k += 4)
-                *reinterpret_cast<uint4*>(ob + 4 * k) =
-                    make_uint4(qb[k], qb[k + 1], qb[k + 2], qb[k + 3]);
-        }
-        return;
+        v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 4;
+        stage_out<4>(wl, ma, 4 * na, out, lane);
+        stage_out<4>(wl, mb, 4 * nb, out + 256, lane);
     } else {
         // OP_ENCODE / OP_ROUNDTRIP: int16 coefficients, natural order.
         uint32_t qa[32], qb[32];
@@ -225,63 +297,67 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
         }
         const bool write_coef = (OP == OP_ENCODE) || (d.flags & F_COEF);
         if (write_coef) {
-            int16_t* oa = reinterpret_cast<int16_t*>(d.coef) + (int64_t)ba * 64;
+            v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 8;
+            v4u m8[8];
 #pragma unroll
-            for (int k = 0; k < 32; k += 4)
-                *reinterpret_cast<uint4*>(oa + 2 * k) =
-                    make_uint4(qa[k], qa[k + 1], qa[k + 2], qa[k + 3]);
-            if (vb) {
-                int16_t* ob = reinterpret_cast<int16_t*>(d.coef) + (int64_t)bb * 64;
+            for (int m = 0; m < 8; ++m) m8[m] = (v4u){qa[4 * m], qa[4 * m + 1], qa[4 * m + 2], qa[4 * m + 3]};
+            stage_out<8>(wl, m8, 8 * na, out, lane);
 #pragma unroll
-                for (int k = 0; k < 32; k += 4)
-                    *reinterpret_cast<uint4*>(ob + 2 * k) =
-                        make_uint4(qb[k], qb[k + 1], qb[k + 2], qb[k + 3]);
-            }
+            for (int m = 0; m < 8; ++m) m8[m] = (v4u){qb[4 * m], qb[4 * m + 1], qb[4 * m + 2], qb[4 * m + 3]};
+            stage_out<8>(wl, m8, 8 * nb, out + 512, lane);
         }
         if constexpr (OP == OP_ROUNDTRIP) {
             uint32_t px[8][2];
-            decode_block(qa, qc, px);
-            store_rows8(const_cast<uint8_t*>(block_ptr(d.dst, d.dst_stride, nbx, ba)),
-                        d.dst_stride, d.flags, px);
+            if (va) {
+                decode_block(qa, qc, px);
+                store_rows8(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+            }
             if (vb) {
                 decode_block(qb, qc, px);
-                store_rows8(const_cast<uint8_t*>(block_ptr(d.dst, d.dst_stride, nbx, bb)),
-                            d.dst_stride, d.flags, px);
+                store_rows8(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
             }
         }
     }
 }
 
 // ---- decoder tile -----------------------------------------------------------
+//
+// Lane l owns block first + l.
 
 template <class QC>
 __device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
-                                         uint32_t count, int lane) {
-    if ((uint32_t)lane >= count) return;
-    const uint32_t b = first + (uint32_t)lane;
-    const int16_t* src = reinterpret_cast<const int16_t*>(d.coef) + (int64_t)b * 64;
+                                         uint32_t count, uint32_t lane, v4u* wl) {
+    v4u mine[8];
+    stage_in(wl, reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, mine);
+    if (lane >= count) return;
     uint32_t qp[32];
 #pragma unroll
-    for (int k = 0; k < 32; k += 4) {
-        uint4 v = *reinterpret_cast<const uint4*>(src + 2 * k);
-        qp[k] = v.x;
-        qp[k + 1] = v.y;
-        qp[k + 2] = v.z;
-        qp[k + 3] = v.w;
+    for (int m = 0; m < 8; ++m) {
+        qp[4 * m] = mine[m].x;
+        qp[4 * m + 1] = mine[m].y;
+        qp[4 * m + 2] = mine[m].z;
+        qp[4 * m + 3] = mine[m].w;
     }
     uint32_t px[8][2];
     decode_block(qp, qc, px);
-    store_rows8(const_cast<uint8_t*>(block_ptr(d.dst, d.dst_stride, (uint32_t)d.nbx, b)),
-                d.dst_stride, d.flags, px);
+    const uint32_t b = first + lane;
+    store_rows8(d.dst + block_offset(d.dst_stride, (uint32_t)d.nbx, b), d.dst_stride, d.flags, px);
 }
 
 template <int OP, class QC>
 __device__ __forceinline__ void run_tile(const ImgDesc& d, const QC& qc, uint32_t first,
-                                         uint32_t count, int lane) {
+                                         uint32_t count, uint32_t lane, v4u* wl) {
     if constexpr (OP == OP_DECODE)
-        dec_tile(d, qc, first, count, lane);
+        dec_tile(d, qc, first, count, lane, wl);
     else
-        enc_tile<OP>(d, qc, first, count, lane);
+        enc_tile<OP>(d, qc, first, count, lane, wl);
+}
+
+// LDS bytes one wave needs for a set of ops (bit i = op i).
+__host__ __device__ constexpr uint32_t lds_wave_bytes(int ops) {
+    return (ops & ((1 << OP_ENCODE) | (1 << OP_ROUNDTRIP) | (1 << OP_DECODE))) ? 8192u
+           : (ops & (1 << OP_ENCODE_I8ZZ)) ? 4096u
+                                           : 0u;
 }
 
 // ---- kernels -----------------------------------------------------------------
@@ -291,30 +367,36 @@ __device__ __forceinline__ void run_tile(const ImgDesc& d, const QC& qc, uint32_
 template <int OP>
 __global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QConst qc,
                                                     uint32_t ntiles) {
+    extern __shared__ v4u lds[];
+    v4u* wl = lds + (threadIdx.x >> 6) * (lds_wave_bytes(1 << OP) / 16);
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpg + (threadIdx.x >> 6));
     const uint32_t nwaves = gridDim.x * wpg;
-    const int lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63;
     constexpr uint32_t TB = OP == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
     const uint32_t nblk = (uint32_t)d.nblk;
     for (uint32_t t = wave; t < ntiles; t += nwaves) {
         const uint32_t first = t * TB;
         const uint32_t count = min(TB, nblk - first);
-        run_tile<OP>(d, qc, first, count, lane);
+        run_tile<OP>(d, qc, first, count, lane, wl);
     }
 }
 
 // Many images: tiles come from a table; each tile names its image, whose
 // descriptor and quantiser constants are read with scalar loads (the tile is
-// image-uniform, so they are the same for the whole wave).
-__global__ __launch_bounds__(1024) void batch_kernel(const Tile* __restrict__ tiles,
+// image-uniform, so they are the same for the whole wave). OPS is the set of
+// ops the plan contains; single-op plans get a kernel with just that path.
+template <int OPS>
+__global__ __launch_bounds__(512) void batch_kernel(const Tile* __restrict__ tiles,
                                                      const ImgDesc* __restrict__ imgs,
                                                      const QConst* __restrict__ qcs,
                                                      uint32_t ntiles, uint32_t tile_waves) {
+    extern __shared__ v4u lds[];
+    v4u* wl = lds + (threadIdx.x >> 6) * (lds_wave_bytes(OPS) / 16);
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpg + (threadIdx.x >> 6));
     const uint32_t nwaves = gridDim.x * wpg;
-    const int lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63;
     // A wave takes `tile_waves` consecutive tiles per step.
     for (uint32_t t0 = wave * tile_waves; t0 < ntiles; t0 += nwaves * tile_waves) {
         const uint32_t tend = min(t0 + tile_waves, ntiles);
@@ -322,12 +404,28 @@ __global__ __launch_bounds__(1024) void batch_kernel(const Tile* __restrict__ ti
             const Tile tl = tiles[t];
             const ImgDesc& d = imgs[tl.img];
             const QConst& qc = qcs[d.qidx];
-            switch (d.op) {
-                case OP_ENCODE: run_tile<OP_ENCODE>(d, qc, tl.first_lo, tl.count, lane); break;
-                case OP_DECODE: run_tile<OP_DECODE>(d, qc, tl.first_lo, tl.count, lane); break;
-                case OP_ROUNDTRIP: run_tile<OP_ROUNDTRIP>(d, qc, tl.first_lo, tl.count, lane); break;
-                case OP_ENCODE_I8ZZ: run_tile<OP_ENCODE_I8ZZ>(d, qc, tl.first_lo, tl.count, lane); break;
-                default: run_tile<OP_FORWARD>(d, qc, tl.first_lo, tl.count, lane); break;
+            const int op = (OPS & (OPS - 1)) == 0 ? __builtin_ctz(OPS) : d.op;
+            switch (op) {
+                case OP_ENCODE:
+                    if constexpr ((OPS >> OP_ENCODE) & 1)
+                        run_tile<OP_ENCODE>(d, qc, tl.first_lo, tl.count, lane, wl);
+                    break;
+                case OP_DECODE:
+                    if constexpr ((OPS >> OP_DECODE) & 1)
+                        run_tile<OP_DECODE>(d, qc, tl.first_lo, tl.count, lane, wl);
+                    break;
+                case OP_ROUNDTRIP:
+                    if constexpr ((OPS >> OP_ROUNDTRIP) & 1)
+                        run_tile<OP_ROUNDTRIP>(d, qc, tl.first_lo, tl.count, lane, wl);
+                    break;
+                case OP_ENCODE_I8ZZ:
+                    if constexpr ((OPS >> OP_ENCODE_I8ZZ) & 1)
+                        run_tile<OP_ENCODE_I8ZZ>(d, qc, tl.first_lo, tl.count, lane, wl);
+                    break;
+                default:
+                    if constexpr ((OPS >> OP_FORWARD) & 1)
+                        run_tile<OP_FORWARD>(d, qc, tl.first_lo, tl.count, lane, wl);
+                    break;
             }
         }
     }
@@ -404,9 +502,30 @@ int image_flags(const ImgDesc& d) {
     int f = 0;
     const uintptr_t s = (uintptr_t)d.src, t = (uintptr_t)d.dst;
     if (d.src && (s % 8 == 0) && (d.src_stride % 8 == 0)) f |= F_SRC8;
-    if (d.src && (s % 16 == 0) && (d.src_stride % 16 == 0) && (d.nbx % 2 == 0)) f |= F_SRC16;
     if (d.dst && (t % 8 == 0) && (d.dst_stride % 8 == 0)) f |= F_DST8;
     return f;
+}
+
+// Dynamic LDS above 64 KB per workgroup has to be enabled per kernel.
+template <typename K>
+static int allow_lds(K kernel, uint32_t bytes) {
+    if (bytes <= 65536) return TDCT_OK;
+    static int device_max = 0;
+    if (!device_max) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&device_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess)
+            device_max = 65536;
+    }
+    if ((int)bytes > device_max) return TDCT_EINVAL;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) {
+        set_error("dynamic LDS attribute", e);
+        return TDCT_EDEVICE;
+    }
+    return TDCT_OK;
 }
 
 template <int OP>
@@ -415,7 +534,8 @@ static int launch_plain(const ImgDesc& d, const QConst& qc, hipStream_t stream) 
     const uint32_t ntiles = (uint32_t)((d.nblk + TB - 1) / TB);
     const uint32_t wpg = 4;
     const uint32_t grid = (ntiles + wpg - 1) / wpg;
-    hipLaunchKernelGGL(plain_kernel<OP>, dim3(grid), dim3(64 * wpg), 0, stream, d, qc, ntiles);
+    const uint32_t lds = wpg * lds_wave_bytes(1 << OP);
+    hipLaunchKernelGGL(plain_kernel<OP>, dim3(grid), dim3(64 * wpg), lds, stream, d, qc, ntiles);
     return check_launch("plain kernel launch");
 }
 
@@ -430,9 +550,10 @@ int launch_plain_op(int op, const ImgDesc& d, const QConst& qc, hipStream_t stre
     return TDCT_EINVAL;
 }
 
-int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
-                 const tdct_tune& tune, int num_cus, hipStream_t stream) {
-    if (ntiles == 0) return TDCT_OK;
+template <int OPS>
+static int launch_batch_ops(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs,
+                            uint32_t ntiles, const tdct_tune& tune, int num_cus,
+                            hipStream_t stream) {
     const uint32_t wpg = (uint32_t)tune.waves_per_group;
     const uint32_t tw = (uint32_t)tune.tile_waves;
     const uint32_t steps = (ntiles + tw - 1) / tw;
@@ -440,9 +561,33 @@ int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint
     const uint32_t need = (steps + wpg - 1) / wpg;
     if (grid > need) grid = need;
     if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(64 * wpg), 0, stream, tiles, imgs, qcs,
+    const uint32_t lds = wpg * lds_wave_bytes(OPS);
+    int st = allow_lds(batch_kernel<OPS>, lds);
+    if (st) return st;
+    hipLaunchKernelGGL(batch_kernel<OPS>, dim3(grid), dim3(64 * wpg), lds, stream, tiles, imgs, qcs,
                        ntiles, tw);
     return check_launch("batch kernel launch");
+}
+
+uint32_t batch_lds_bytes(int ops, int waves_per_group) {
+    return (uint32_t)waves_per_group * lds_wave_bytes(ops);
+}
+
+int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
+                 int ops, const tdct_tune& tune, int num_cus, hipStream_t stream) {
+    if (ntiles == 0) return TDCT_OK;
+    constexpr int E = 1 << OP_ENCODE, D = 1 << OP_DECODE, R = 1 << OP_ROUNDTRIP,
+                  Z = 1 << OP_ENCODE_I8ZZ, F = 1 << OP_FORWARD;
+    switch (ops) {
+        case E: return launch_batch_ops<E>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+        case D: return launch_batch_ops<D>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+        case R: return launch_batch_ops<R>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+        case Z: return launch_batch_ops<Z>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+        case F: return launch_batch_ops<F>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+        case E | D: return launch_batch_ops<E | D>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+        default:
+            return launch_batch_ops<E | D | R | Z | F>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+    }
 }
 
 int fill_desc(int op, const uint8_t* src, int64_t src_stride, int32_t w, int32_t h, void* coef,

@@ -227,6 +227,7 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
         std::vector<ImgDesc> imgs((size_t)n);
         std::vector<QConst> qcs((size_t)n);
         std::vector<Tile> tiles;
+        int ops = 0;
         for (int i = 0; i < n; ++i) {
             const tdct_request& r = items[i].r;
             make_qconst(&r.Q, r.op == TDCT_OP_ENCODE ? r.keep : 64, &qcs[i]);
@@ -236,6 +237,7 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
             else
                 fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(r.input),
                           (uint8_t*)items[i].out, r.w, i, false, &imgs[i]);
+            ops |= 1 << imgs[i].op;
             const int tb = tile_blocks(imgs[i].op);
             for (int64_t f = 0; f < imgs[i].nblk; f += tb) {
                 Tile t;
@@ -263,7 +265,7 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
         }
         char* dbase = (char*)sl.dev;
         st = launch_batch((const Tile*)dbase, (const ImgDesc*)(dbase + tb),
-                          (const QConst*)(dbase + tb + ib), (uint32_t)tiles.size(), s->cfg.tune,
+                          (const QConst*)(dbase + tb + ib), (uint32_t)tiles.size(), ops, s->cfg.tune,
                           s->num_cus, sl.stream);
         if (st) return st;
     }

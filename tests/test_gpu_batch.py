@@ -120,7 +120,8 @@ def test_graph_replays_equal_direct_launch(tdct):
 @pytest.mark.parametrize("tune", [dict(waves_per_group=1, groups_per_cu=1, tile_waves=1),
                                   dict(waves_per_group=2, groups_per_cu=3, tile_waves=2),
                                   dict(waves_per_group=8, groups_per_cu=4, tile_waves=4),
-                                  dict(waves_per_group=16, groups_per_cu=2, tile_waves=1)])
+                                  dict(waves_per_group=8, groups_per_cu=4096, tile_waves=1),
+                                  dict(waves_per_group=1, groups_per_cu=4096, tile_waves=2)])
 def test_every_launch_shape_gives_same_bytes(tdct, tune):
     R = Ragged(tdct, seed=7)
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs, tune=tune)
