@@ -246,8 +246,10 @@ void tdct_server_destroy(tdct_server* s);
 
 /* Open-loop replay: request k is submitted at arrival_us[k] after the call
  * starts (host clock); outputs are released as they complete unless
- * keep_outputs. latency_us[k] receives submit -> completion; status[k] the
- * final status. Returns after every request has completed. */
+ * keep_outputs (then the caller releases the tickets, and TDCT_ENOMEM is
+ * returned up front when all outputs together exceed the budget).
+ * latency_us[k] receives submit -> completion; status[k] the final status.
+ * Returns after every request has completed. */
 int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us,
                        int32_t n, int32_t keep_outputs, uint64_t* tickets_out,
                        double* latency_us, int32_t* status);

@@ -598,10 +598,15 @@ int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* a
                        int32_t keep_outputs, uint64_t* tickets_out, double* latency_us,
                        int32_t* status) {
     if (!s || n < 0 || (n > 0 && (!reqs || !arrival_us))) return TDCT_EINVAL;
+    int64_t kept = 0;
     for (int32_t k = 0; k < n; ++k) {
         int st = validate_request(reqs[k]);
         if (st) return st;
+        kept += Arena::round(output_bytes(reqs[k]));
     }
+    // Kept outputs are released only after this call returns, so they must
+    // all fit at once, or admission would wait forever.
+    if (keep_outputs && kept > s->arena->size()) return TDCT_ENOMEM;
     std::vector<uint64_t> tk((size_t)n, 0);
     std::vector<int32_t> sub((size_t)n, TDCT_OK);
     const Clock::time_point start = Clock::now();

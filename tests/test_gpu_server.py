@@ -1,0 +1,148 @@
+"""Serving form on the GPU: a Poisson mix of encode and decode requests of
+uneven sizes, admitted under a budget and continuously batched over several
+streams. Every request's output in the mix must be byte-identical to the
+same request served alone (tolerance 0), sampled requests must equal the
+oracle, and the arena must never exceed its budget."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import sync
+
+pytestmark = pytest.mark.gpu
+
+POOL_SIDE = 1024
+
+
+@pytest.fixture(scope="module")
+def tdct():
+    import paper_1702_00817_amd as m
+    return m
+
+
+def _hip():
+    import torch
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+    lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    lib.hipMemcpy.restype = ctypes.c_int
+    return lib
+
+
+def _read(hip, ptr, nbytes):
+    out = np.empty(nbytes, np.uint8)
+    assert hip.hipMemcpy(out.ctypes.data, ptr, nbytes, 2) == 0  # device -> host
+    return out
+
+
+class Workload:
+    def __init__(self, tdct, rate=3000.0, seconds=0.12, seed=55):
+        import torch
+        rng = np.random.default_rng(seed)
+        self.planes = [synth.plane(POOL_SIDE, POOL_SIDE, 7000 + k) for k in range(2)]
+        self.coefs = [rng.integers(-300, 301, size=((POOL_SIDE // 8) ** 2, 64)).astype(np.int16)
+                      for _ in range(2)]
+        self.dplanes = [torch.from_numpy(p).cuda() for p in self.planes]
+        self.dcoefs = [torch.from_numpy(c).cuda() for c in self.coefs]
+        tr = synth.serving_trace(rate, seconds, seed=seed, lo=32, hi=POOL_SIDE)
+        self.tr = tr
+        self.reqs, self.meta = [], []
+        for k in range(len(tr["t"])):
+            w, h, s, op = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k]), int(tr["op"][k])
+            p = k % 2
+            Q = synth.qtable(1, s)
+            keep = 64 if k % 5 else 10
+            if op == 0:
+                r = tdct.request(tdct.OP_ENCODE, w, h, self.dplanes[p], Q, keep=keep, in_stride=POOL_SIDE)
+                nbytes = w * h * 2
+            else:
+                r = tdct.request(tdct.OP_DECODE, w, h, self.dcoefs[p], Q)
+                nbytes = w * h
+            self.reqs.append(r)
+            self.meta.append(dict(op=op, w=w, h=h, p=p, Q=Q, keep=keep, nbytes=nbytes))
+        self.arrival = (tr["t"] * 1e6).tolist()
+
+    def expected(self, k):
+        m = self.meta[k]
+        if m["op"] == 0:
+            img = np.ascontiguousarray(self.planes[m["p"]][:m["h"], :m["w"]])
+            return O.quantise(img, m["Q"], m["keep"]).view(np.uint8).reshape(-1)
+        nblk = (m["w"] // 8) * (m["h"] // 8)
+        return O.inverse(self.coefs[m["p"]][:nblk], m["Q"], m["w"], m["h"]).reshape(-1)
+
+
+def _serve(tdct, W, cfg, idx=None, arrival=True):
+    hip = _hip()
+    srv = tdct.tdct_server_create(cfg)
+    try:
+        reqs = W.reqs if idx is None else [W.reqs[k] for k in idx]
+        arr = W.arrival if (idx is None and arrival) else [0.0] * len(reqs)
+        tickets, lat, st = tdct.tdct_server_replay(srv, reqs, arr, keep_outputs=True)
+        outs = []
+        for t, s_ in zip(tickets, st):
+            assert s_ == tdct.TDCT_OK
+            r = tdct.tdct_server_poll(srv, t)
+            outs.append(_read(hip, r.output, r.output_bytes))
+        stats = tdct.tdct_server_stats(srv)
+        for t in tickets:
+            tdct.tdct_server_release(srv, t)
+        assert tdct.tdct_server_stats(srv)["arena_bytes_in_use"] == 0
+        return outs, lat, stats
+    finally:
+        tdct.tdct_server_destroy(srv)
+
+
+def test_mix_equals_alone_and_oracle(tdct):
+    W = Workload(tdct, rate=10000.0, seconds=0.03)
+    n = len(W.reqs)
+    assert n > 100
+    budget = 1 << 30
+    cfg = tdct.server_cfg(budget, streams=4, max_batch=16, max_wait_us=300, batching=1)
+    mix, lat, stats = _serve(tdct, W, cfg)
+    assert stats["completed"] == n and stats["failed"] == 0
+    assert stats["arena_high_water"] <= budget
+    assert stats["mean_batch"] > 1.0  # requests really shared launches
+    # alone: each request on its own, one at a time, through a fresh server
+    alone_cfg = tdct.server_cfg(budget, streams=1, max_batch=1, batching=1)
+    for k in range(n):
+        out, _, _ = _serve(tdct, W, alone_cfg, idx=[k])
+        assert np.array_equal(mix[k], out[0]), k
+    # per-request plain launches give the same bytes too
+    per, _, st2 = _serve(tdct, W, tdct.server_cfg(budget, streams=4, max_batch=1, batching=0))
+    assert st2["mean_batch"] == 1.0
+    for k in range(n):
+        assert np.array_equal(mix[k], per[k]), k
+    # oracle on a sample (and on every request that is small)
+    rng = np.random.default_rng(1)
+    sample = set(rng.choice(n, 40, replace=False).tolist()) | {k for k in range(n) if
+                                                              W.meta[k]["w"] * W.meta[k]["h"] <= 64 * 64}
+    for k in sorted(sample):
+        assert np.array_equal(mix[k], W.expected(k)), k
+
+
+def test_tight_budget_queues_instead_of_failing(tdct):
+    """A budget that holds only the largest output: requests wait in FIFO
+    order for memory and all complete once earlier outputs are released."""
+    W = Workload(tdct, rate=20000.0, seconds=0.01, seed=56)
+    biggest = max(m["nbytes"] for m in W.meta)
+    budget = (biggest + 255) // 256 * 256 + 256
+    hip = _hip()
+    srv = tdct.tdct_server_create(tdct.server_cfg(budget, streams=2, max_batch=8, batching=1))
+    try:
+        tickets = [tdct.tdct_server_submit(srv, r) for r in W.reqs]
+        for k, t in enumerate(tickets):
+            r = tdct.tdct_server_wait(srv, t)
+            assert r.status == tdct.TDCT_OK
+            assert np.array_equal(_read(hip, r.output, r.output_bytes), W.expected(k)), k
+            tdct.tdct_server_release(srv, t)
+        st = tdct.tdct_server_stats(srv)
+        assert st["failed"] == 0 and st["arena_high_water"] <= budget
+        # replay keeping every output cannot fit this budget: refused, not hung
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_replay(srv, W.reqs, [0.0] * len(W.reqs), keep_outputs=True)
+        assert e.value.status == tdct.TDCT_ENOMEM
+    finally:
+        tdct.tdct_server_destroy(srv)
