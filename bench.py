@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MAX_BATCH_PX = 64 << 20  # serving: a launch stops growing at 64 Mpx (~35 us of HBM time)
 
 
 def log(msg):
@@ -100,26 +101,26 @@ def time_steps(tdct, torch, pe, pd, steps, warmup, stream):
     return wall, enc_ms, dec_ms
 
 
-def cpu_baseline(W, budget_s=15.0):
+def cpu_baseline(W, min_s=10.0, max_passes=16):
     """The oracle, as it stands, on the host cores: encode + decode of whole
-    4096 x 4096 images from the same batch, one after another, until the
-    time budget is spent (at least one image)."""
-    import numpy as np
-
+    4096 x 4096 images of the same batch, cycling through the batch until at
+    least `min_s` seconds have passed (at most `max_passes` passes)."""
     import oracle as O
     import synth
     threads = max(1, min(os.cpu_count() or 1, 64))
     px = 0
     done = 0
+    n = len(W["sizes"])
     t0 = time.perf_counter()
-    for i in range(len(W["sizes"])):
+    while done < max_passes * n:
+        i = done % n
         img = synth.batch_view(W["buf"], W["off"], W["strides"], W["sizes"], i)
         w, h = W["sizes"][i]
         q = O.quantise(img, W["qs"][i], 64, threads=threads)
         O.inverse(q, W["qs"][i], w, h, threads=threads)
         px += w * h
         done += 1
-        if time.perf_counter() - t0 > budget_s:
+        if time.perf_counter() - t0 >= min_s:
             break
     dt = time.perf_counter() - t0
     cpu_model = ""
@@ -130,10 +131,9 @@ def cpu_baseline(W, budget_s=15.0):
                 break
     except OSError:
         pass
-    del np
     return {"value": round(px / dt / 1e9, 4), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
-            "sample": "encode+decode of %d of the %d 4096x4096 images (%.1f s wall), dense 8x8 "
-                      "integer products, %d threads, %s" % (done, len(W["sizes"]), dt, threads, cpu_model)}
+            "sample": "encode+decode of %d images of 4096x4096 from the 64-image batch (%.1f s wall), "
+                      "dense 8x8 integer products, %d threads, %s" % (done, dt, threads, cpu_model)}
 
 
 def batched_leg(tdct, torch, stream, n=10000, reps=5):
@@ -183,6 +183,115 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
             "speedup": round(per_s / graph_s, 2), "bytes_per_px": 4}
 
 
+def ceiling_leg(tdct, torch, stream, mib=1024, reps=5):
+    """HBM ceilings on this part: the codec's access mixes without arithmetic."""
+    units = (mib << 20) // 16
+    a = torch.ones(2 * units * 16, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for kind, name, per_unit in ((tdct.PROBE_COPY, "copy", 32), (tdct.PROBE_READ, "read", 16),
+                                 (tdct.PROBE_WRITE, "write", 16), (tdct.PROBE_R1W2, "read1_write2", 48),
+                                 (tdct.PROBE_R2W1, "read2_write1", 48)):
+        tdct.tdct_stream_probe(kind, a, b, units, stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        for k in range(reps):
+            ev[k].record(stream)
+            tdct.tdct_stream_probe(kind, a, b, units, stream)
+        ev[reps].record(stream)
+        torch.cuda.synchronize()
+        ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))[reps // 2]
+        out[name] = round(per_unit * units / (ms / 1e3) / 1e9, 1)
+    del a, b
+    return {"unit": "GB/s", "mib_per_unit_side": mib, **out}
+
+
+def fused_leg(tdct, torch, W, stream, reps=10):
+    """Encode + decode in one pass with no coefficients in HBM (2 B/px) on the
+    same 64 x 4096^2 batch."""
+    n = len(W["sizes"])
+    side = W["sizes"][0][0]
+    base = W["src"].data_ptr()
+    descs = [tdct.image_desc(tdct.OP_ROUNDTRIP, side, side, qtab=i, keep=64, src=base + int(W["off"][i]),
+                             src_stride=side, coef=None, dst=W["dst"][i], dst_stride=side)
+             for i in range(n)]
+    plan = tdct.tdct_batch_plan(descs, W["qs"])
+    try:
+        tune = tdct.tdct_autotune(plan, stream, reps=2)
+        tdct.tdct_batch_run(plan, stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        for k in range(reps):
+            ev[k].record(stream)
+            tdct.tdct_batch_run(plan, stream)
+        ev[reps].record(stream)
+        torch.cuda.synchronize()
+        ms = sum(ev[k].elapsed_time(ev[k + 1]) for k in range(reps)) / reps
+    finally:
+        tdct.tdct_plan_free(plan)
+    px = W["pixels"]
+    return {"kernel": "batch_kernel<4> (round trip, coefficients kept in registers)", "tune": tune,
+            "ms": round(ms, 4), "gpx_s": round(px / (ms / 1e3) / 1e9, 1),
+            "gbs": round(2 * px / (ms / 1e3) / 1e9, 1), "bytes_per_px": 2}
+
+
+def video_leg(tdct, torch, stream, frames=256, reps=5):
+    """256 frames of 3840x2160 4:2:0: encoder with luma/chroma Q tables,
+    int8-saturated zigzag coefficients; one persistent launch over all
+    768 planes (graph replay) vs one plain launch per plane."""
+    import numpy as np
+
+    import synth
+    v = synth.Video420(frames=frames)
+    w, h = v.w, v.h
+    fbytes = w * h + 2 * (w // 2) * (h // 2)
+    t0 = time.time()
+    host = np.empty(frames * fbytes, np.uint8)
+    for f in range(frames):
+        o = f * fbytes
+        Y = host[o:o + w * h].reshape(h, w)
+        Cb = host[o + w * h:o + w * h + (w // 2) * (h // 2)].reshape(h // 2, w // 2)
+        Cr = host[o + w * h + (w // 2) * (h // 2):o + fbytes].reshape(h // 2, w // 2)
+        v.frame(f, out=(Y, Cb, Cr))
+    log("generated %d 4:2:0 frames (%.2f G samples) in %.1fs" % (frames, host.size / 1e9, time.time() - t0))
+    src = torch.from_numpy(host).cuda()
+    out = torch.empty(host.size, dtype=torch.int8, device="cuda")
+    descs, qtabs = [], []
+    sb, ob = src.data_ptr(), out.data_ptr()
+    for f in range(frames):
+        qy, qc = v.qtables(f)
+        qtabs += [qy, qc]
+        o = f * fbytes
+        for pw, ph, po, qi in ((w, h, 0, 2 * f), (w // 2, h // 2, w * h, 2 * f + 1),
+                               (w // 2, h // 2, w * h + (w // 2) * (h // 2), 2 * f + 1)):
+            descs.append(tdct.image_desc(tdct.OP_ENCODE_I8ZZ, pw, ph, qtab=qi, src=sb + o + po,
+                                         src_stride=pw, coef=ob + o + po))
+    plan = tdct.tdct_batch_plan(descs, qtabs)
+    try:
+        tune = tdct.tdct_autotune(plan, stream, reps=2)
+        tdct.tdct_batch_graph(plan, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tdct.tdct_batch_graph(plan, stream)
+        torch.cuda.synchronize()
+        graph_s = (time.perf_counter() - t0) / reps
+        tdct.tdct_run_per_image(descs, qtabs, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tdct.tdct_run_per_image(descs, qtabs, stream)
+        torch.cuda.synchronize()
+        per_s = (time.perf_counter() - t0) / reps
+    finally:
+        tdct.tdct_plan_free(plan)
+    n = host.size
+    del src, out
+    return {"frames": frames, "samples": n, "tune": tune,
+            "graph_gsamples_s": round(n / graph_s / 1e9, 1), "graph_ms": round(graph_s * 1e3, 3),
+            "graph_gbs": round(2 * n / graph_s / 1e9, 1),
+            "per_plane_gsamples_s": round(n / per_s / 1e9, 1), "per_plane_ms": round(per_s * 1e3, 3),
+            "speedup": round(per_s / graph_s, 2), "bytes_per_sample": 2}
+
+
 def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
     """Poisson encode/decode requests with device-resident payloads, served by
     continuous batching and by one plain launch per request."""
@@ -218,7 +327,8 @@ def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
         res = {"requests": len(reqs), "mpx_mean": round(px / max(1, len(reqs)) / 1e6, 3)}
         for mode, batching in (("batched", 1), ("per_request", 0)):
             srv = tdct.tdct_server_create(tdct.server_cfg(64 << 30, streams=streams, max_batch=64,
-                                                          max_wait_us=0, batching=batching))
+                                                          max_wait_us=0, batching=batching,
+                                                          max_batch_px=MAX_BATCH_PX))
             try:
                 t0 = time.perf_counter()
                 _, lat, st = tdct.tdct_server_replay(srv, reqs, arrival)
@@ -232,9 +342,24 @@ def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
                          "p999_us": round(float(np.percentile(lat, 99.9)), 1),
                          "failed": int(sum(1 for s_ in st if s_ != 0)),
                          "delivered_gpx_s": round(px / wall / 1e9, 3),
-                         "busy_gpx_s": round(px / max(stats["busy_us"], 1.0) / 1e3, 2),
                          "batches": stats["batches"], "mean_batch": round(stats["mean_batch"], 2),
                          "arena_high_water_gb": round(stats["arena_high_water"] / 1e9, 3)}
+        if rate == max(rates):
+            # capacity: the same requests all arriving at once (closed burst)
+            for mode, batching in (("batched", 1), ("per_request", 0)):
+                srv = tdct.tdct_server_create(tdct.server_cfg(64 << 30, streams=streams, max_batch=64,
+                                                              max_wait_us=0, batching=batching,
+                                                              max_batch_px=MAX_BATCH_PX))
+                try:
+                    t0 = time.perf_counter()
+                    _, lat, st = tdct.tdct_server_replay(srv, reqs, [0.0] * len(reqs))
+                    wall = time.perf_counter() - t0
+                    stats = tdct.tdct_server_stats(srv)
+                finally:
+                    tdct.tdct_server_destroy(srv)
+                res["burst_" + mode] = {"gpx_s": round(px / wall / 1e9, 1), "wall_ms": round(wall * 1e3, 1),
+                                        "mean_batch": round(stats["mean_batch"], 2),
+                                        "failed": int(sum(1 for s_ in st if s_ != 0))}
         out[str(rate)] = res
         log("serving %d req/s: %s" % (rate, json.dumps(res)))
     return {"seconds_per_rate": seconds, "streams": streams, "budget_gb": 64, "rates": out}
@@ -343,9 +468,17 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)...")
         result["cpu_baseline"] = cpu_baseline(W)
+    if not args.no_extras:
+        log("fused round-trip leg...")
+        result["fused_roundtrip"] = fused_leg(tdct, torch, W, stream)
     del W
     torch.cuda.empty_cache()
     if not args.no_extras:
+        log("ceiling leg...")
+        result["ceiling"] = ceiling_leg(tdct, torch, stream)
+        log("video leg...")
+        result["video"] = video_leg(tdct, torch, stream)
+        torch.cuda.empty_cache()
         log("batched leg...")
         result["batched"] = batched_leg(tdct, torch, stream)
         torch.cuda.empty_cache()

@@ -108,6 +108,19 @@ int tdct_quantise_i8_zigzag(const uint8_t* src, int64_t src_stride, int32_t w, i
 int tdct_sse(const uint8_t* a, int64_t a_stride, const uint8_t* b, int64_t b_stride, int32_t w,
              int32_t h, uint64_t* sse_dev, void* stream);
 
+/* Diagnostics: the HBM ceilings the codec kernels are measured against.
+ * One launch streams `units` 16-byte units with the access mix of `kind`
+ * and no arithmetic, non-temporal like the codec:
+ *   COPY  src[units] -> dst[units]          (2 x 16 B per unit)
+ *   READ  src[units], dst receives 16 B     (16 B per unit)
+ *   WRITE dst[units]                        (16 B per unit)
+ *   R1W2  src[units] -> dst[u] and dst[units + u] (48 B per unit; the encoder's 1:2 mix)
+ *   R2W1  src[u] and src[units + u] -> dst[units] (48 B per unit; the decoder's 2:1 mix)
+ * Device pointers, 16-byte aligned, sized as above. */
+enum { TDCT_PROBE_COPY = 0, TDCT_PROBE_READ = 1, TDCT_PROBE_WRITE = 2, TDCT_PROBE_R1W2 = 3,
+       TDCT_PROBE_R2W1 = 4 };
+int tdct_stream_probe(int32_t kind, const void* src, void* dst, int64_t units, void* stream);
+
 const char* tdct_strerror(int status);
 const char* tdct_last_error(void);
 
@@ -191,6 +204,8 @@ typedef struct {
                               queue holds max_batch requests or the oldest waited this long */
     int32_t batching;      /* 1 = continuous batching into the persistent kernel;
                               0 = one plain launch per request (comparison mode) */
+    int64_t max_batch_px;  /* a batch stops growing once it holds this many pixels, so
+                              small requests do not wait for a huge one (0 = no cap) */
     tdct_tune tune;        /* launch shape of batch launches (zeros = defaults) */
     int32_t fake_device_us; /* > 0: no GPU at all -- outputs live in host memory and a
                                batch "completes" this many microseconds after launch

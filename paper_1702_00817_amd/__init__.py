@@ -70,7 +70,7 @@ class tdct_plan_info(ctypes.Structure):
 class tdct_server_cfg(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
-                ("batching", ctypes.c_int32), ("tune", tdct_tune),
+                ("batching", ctypes.c_int32), ("max_batch_px", ctypes.c_int64), ("tune", tdct_tune),
                 ("fake_device_us", ctypes.c_int32), ("fake_fail_every", ctypes.c_int32)]
 
 
@@ -108,6 +108,7 @@ _SIG = {
     "tdct_roundtrip": [_P, _i64, _i32, _i32, _PQ, _i32, _P, _P, _i64, _P],
     "tdct_quantise_i8_zigzag": [_P, _i64, _i32, _i32, _PQ, _P, _P],
     "tdct_sse": [_P, _i64, _P, _i64, _i32, _i32, _P, _P],
+    "tdct_stream_probe": [_i32, _P, _P, _i64, _P],
     "tdct_batch_plan": [ctypes.POINTER(tdct_image_desc), _i32, _PQ, _i32,
                         ctypes.POINTER(tdct_tune), ctypes.POINTER(_P)],
     "tdct_batch_run": [_P, _P],
@@ -217,6 +218,14 @@ def tdct_sse(a, a_stride, b, b_stride, w, h, sse_dev, stream=None):
                          _stream(stream)), "tdct_sse")
 
 
+PROBE_COPY, PROBE_READ, PROBE_WRITE, PROBE_R1W2, PROBE_R2W1 = 0, 1, 2, 3, 4
+
+
+def tdct_stream_probe(kind, src, dst, units, stream=None):
+    _check(_lib.tdct_stream_probe(kind, _ptr(src), _ptr(dst), units, _stream(stream)),
+           "tdct_stream_probe")
+
+
 def tdct_strerror(status: int) -> str:
     return _lib.tdct_strerror(status).decode()
 
@@ -298,10 +307,10 @@ def tdct_run_per_image(descs, qtabs, stream=None):
 # ---- serving form ------------------------------------------------------------
 
 def server_cfg(budget_bytes, streams=4, max_batch=64, max_wait_us=0, batching=1, tune=None,
-               fake_device_us=0, fake_fail_every=0) -> tdct_server_cfg:
+               fake_device_us=0, fake_fail_every=0, max_batch_px=0) -> tdct_server_cfg:
     c = tdct_server_cfg()
     c.budget_bytes, c.streams, c.max_batch = budget_bytes, streams, max_batch
-    c.max_wait_us, c.batching = max_wait_us, batching
+    c.max_wait_us, c.batching, c.max_batch_px = max_wait_us, batching, max_batch_px
     if tune:
         c.tune = tdct_tune(**tune)
     c.fake_device_us, c.fake_fail_every = fake_device_us, fake_fail_every

@@ -116,18 +116,31 @@ constexpr Zigzag kZigzag = make_zigzag();
 
 // ---- quantiser --------------------------------------------------------------
 //
-// q = round-half-away(W / Q) with W = y * 2^s, evaluated as
-//   q = floor(fma(float(y), r, 0.5)),  r = fl32(2^s / Q * (1 + 2^-20)).
-// The relative bias 2^-20 on r moves every exact tie z = W / Q = k + 1/2 away
-// from zero by about |z| 2^-20, which is more than the rounding of r and of
-// the fma (each <= 2^-24 relative), so ties round away from zero; every
-// non-tie lies at least 1 / (2Q) from a rounding boundary, and the bias plus
-// rounding stays below |z| 1.2e-6 + 3e-8 <= 0.0098 / Q for |W| <= 8192. A
-// position outside the zonal set uses r = 0 and yields 0. The host test runs
-// this over every (y, s, Q) of the encoder's domain against the exact
-// rational rounding.
-__host__ __device__ __forceinline__ int quant_f32(int y, float r) {
-    return (int)floorf(fmaf((float)y, r, 0.5f));
+// q = round-half-away(W / Q) with W = y * 2^s, evaluated as one fma whose
+// addend is M = 1.5 * 2^23:
+//   t = fma(float(y), r, M),  r = fl32(2^s / Q * (1 + 2^-20)),
+// t is M + y r rounded once to the nearest integer (|y r| < 2^22, so the
+// result lies in (2^23, 2^24), where floats are spaced by exactly 1), and the
+// integer is q = bits(t) - bits(M). Since bits(M) = 0x4B400000 has zero low
+// halves, the low 16 bits of t are q itself, ready to pack.
+// Why the rounding is exact: the relative bias 2^-20 on r moves every exact
+// tie z = W / Q = k + 1/2 away from zero by about |z| 2^-20, more than the
+// rounding of r (2^-24 relative), so ties round away from zero; every other z
+// lies at least 1 / (2Q) from a half-integer while the bias and r's rounding
+// stay below |z| 1.1e-6 <= 0.0091 / Q for |W| <= 8192, so no such z is pushed
+// onto or across one (and y r itself is never a half-integer: it would have
+// to be one of these two cases). A position outside the zonal set has r = 0,
+// t = M and q = 0. The host test sweeps every (y, s, Q) of the encoder's
+// domain against the exact rational rounding.
+constexpr float kRoundMagic = 12582912.0f;  // 1.5 * 2^23
+constexpr uint32_t kRoundMagicBits = 0x4B400000u;
+
+__host__ __device__ __forceinline__ uint32_t quant_bits(int y, float r) {
+    return __builtin_bit_cast(uint32_t, fmaf((float)y, r, kRoundMagic));
+}
+
+__host__ __device__ __forceinline__ int quant_int(int y, float r) {
+    return (int)(quant_bits(y, r) - kRoundMagicBits);
 }
 
 // Host-side constant for position (i, j): r as above, or 0 if masked.

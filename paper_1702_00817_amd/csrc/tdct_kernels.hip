@@ -275,8 +275,12 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int k = kZigzag.order[n + 4 * g + t];
-                    a4[t] = min(max(quant_f32(v[k].x, qc.r[k]), -128), 127) & 0xff;
-                    b4[t] = min(max(quant_f32(v[k].y, qc.r[k]), -128), 127) & 0xff;
+                    // t's bits grow with q, so saturating them saturates q;
+                    // the low byte is then q's two's-complement byte.
+                    a4[t] = (int)(min(max(quant_bits(v[k].x, qc.r[k]), kRoundMagicBits - 128u),
+                                      kRoundMagicBits + 127u) & 0xffu);
+                    b4[t] = (int)(min(max(quant_bits(v[k].y, qc.r[k]), kRoundMagicBits - 128u),
+                                      kRoundMagicBits + 127u) & 0xffu);
                 }
                 wa[g] = pack8(a4[0], a4[1], a4[2], a4[3]);
                 wb[g] = pack8(b4[0], b4[1], b4[2], b4[3]);
@@ -292,8 +296,8 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
         uint32_t qa[32], qb[32];
 #pragma unroll
         for (int k = 0; k < 64; k += 2) {
-            qa[k / 2] = pack16(quant_f32(v[k].x, qc.r[k]), quant_f32(v[k + 1].x, qc.r[k + 1]));
-            qb[k / 2] = pack16(quant_f32(v[k].y, qc.r[k]), quant_f32(v[k + 1].y, qc.r[k + 1]));
+            qa[k / 2] = pack16((int)quant_bits(v[k].x, qc.r[k]), (int)quant_bits(v[k + 1].x, qc.r[k + 1]));
+            qb[k / 2] = pack16((int)quant_bits(v[k].y, qc.r[k]), (int)quant_bits(v[k + 1].y, qc.r[k + 1]));
         }
         const bool write_coef = (OP == OP_ENCODE) || (d.flags & F_COEF);
         if (write_coef) {

@@ -137,6 +137,7 @@ struct tdct_server {
     tdct_stats st{};
     std::vector<double> lat;
     double busy_since = -1;
+    double last_activity_us = -1e30;  // last submit, admission, launch or completion
     Clock::time_point t0;
     char err[256] = {0};
 
@@ -207,8 +208,9 @@ struct BatchItem {
 int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>& items) {
     if (s->fake) return TDCT_OK;
     const int n = (int)items.size();
-    if (!s->cfg.batching) {
-        // Per-request plain launches (comparison mode): one request per slot.
+    if (!s->cfg.batching || n == 1) {
+        // Plain launches with everything in the kernel arguments: the
+        // comparison mode, and a batch of one (no tables to upload).
         for (const BatchItem& it : items) {
             const tdct_request& r = it.r;
             QConst qc;
@@ -298,6 +300,10 @@ void finish_request(tdct_server* s, uint64_t t, int status, int batch_size, doub
     }
 }
 
+// How long the scheduler keeps polling after the last activity before it
+// sleeps on its condition variable.
+constexpr double kSpinUs = 2000.0;
+
 void scheduler(tdct_server* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     std::vector<BatchItem> items;
@@ -318,6 +324,7 @@ void scheduler(tdct_server* s) {
                 if (fired && e != hipSuccess) status = TDCT_EDEVICE;
             }
             if (fired) {
+                s->last_activity_us = now;
                 const int bs = (int)sl.tickets.size();
                 for (uint64_t t : sl.tickets) finish_request(s, t, status, bs, now);
                 sl.tickets.clear();
@@ -337,8 +344,21 @@ void scheduler(tdct_server* s) {
         while (!s->waiting.empty()) {
             Req& q = s->reqs[s->waiting.front()];
             const int64_t off = s->arena->alloc(q.out_bytes);
-            if (off < 0) break;
+            if (off < 0) {
+                // Shutting down with nothing left in flight: the memory this
+                // request waits for is held by outputs the client never
+                // released, so it can never be admitted.
+                if (s->stop && !any_busy && s->admitted.empty()) {
+                    const uint64_t t = s->waiting.front();
+                    s->waiting.pop_front();
+                    finish_request(s, t, TDCT_EBUSY, 0, now);
+                    s->done.notify_all();
+                    continue;
+                }
+                break;
+            }
             q.arena_off = off;
+            s->last_activity_us = now;
             s->admitted.push_back(s->waiting.front());
             s->waiting.pop_front();
         }
@@ -356,14 +376,20 @@ void scheduler(tdct_server* s) {
                 break;
             }
             items.clear();
+            int64_t batch_px = 0;
             while (!s->admitted.empty() && (int)items.size() < maxb) {
                 const uint64_t t = s->admitted.front();
-                s->admitted.pop_front();
                 Req& q = s->reqs[t];
+                const int64_t px = (int64_t)q.r.w * q.r.h;
+                if (!items.empty() && s->cfg.max_batch_px > 0 && batch_px + px > s->cfg.max_batch_px)
+                    break;
+                batch_px += px;
+                s->admitted.pop_front();
                 items.push_back({t, q.r, s->arena_base + q.arena_off});
                 sl.tickets.push_back(t);
             }
             sl.busy = true;
+            s->last_activity_us = now;
             s->batches++;
             s->batch_reqs += (int64_t)items.size();
             sl.launched_us = now;
@@ -385,20 +411,25 @@ void scheduler(tdct_server* s) {
             }
         }
         if (s->stop && s->in_flight == 0) break;
-        // Sleep until something can change: a submit, a completion (polled),
-        // or the batching deadline.
+        // While batches are in flight, or shortly after any activity, poll:
+        // event completion and new arrivals are seen within microseconds.
+        // Otherwise sleep until a submit, a release or the batching deadline.
         bool busy_now = false;
         for (Slot& sl : s->slots) busy_now |= sl.busy;
-        if (busy_now) {
-            s->wake.wait_for(lk, std::chrono::microseconds(5));
-        } else if (next_deadline >= 0) {
-            const double dt = std::max(1.0, next_deadline - s->now_us());
+        const double tnow = s->now_us();
+        if (busy_now || tnow - s->last_activity_us < kSpinUs) {
+            if (next_deadline < 0 || busy_now || next_deadline - tnow < kSpinUs) {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+                continue;
+            }
+        }
+        if (next_deadline >= 0) {
+            const double dt = std::max(1.0, next_deadline - tnow);
             s->wake.wait_for(lk, std::chrono::microseconds((int64_t)dt));
-        } else if (s->admitted.empty() && s->waiting.empty() && !s->stop) {
-            s->wake.wait_for(lk, std::chrono::milliseconds(50));
-        } else if (!s->waiting.empty() && s->admitted.empty()) {
-            // waiting for arena space that only a release can free
-            s->wake.wait_for(lk, std::chrono::milliseconds(5));
+        } else if (!s->stop) {
+            s->wake.wait_for(lk, std::chrono::milliseconds(10));
         }
     }
     if (s->busy_since >= 0) s->st.busy_us += s->now_us() - s->busy_since;
@@ -412,7 +443,7 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
     if (!cfg || !out) return TDCT_EINVAL;
     *out = nullptr;
     if (cfg->budget_bytes <= 0 || cfg->streams < 1 || cfg->streams > 16 || cfg->max_batch < 0 ||
-        cfg->max_wait_us < 0)
+        cfg->max_wait_us < 0 || cfg->max_batch_px < 0)
         return TDCT_EINVAL;
     tdct_server* s = new (std::nothrow) tdct_server();
     if (!s) return TDCT_ENOMEM;
@@ -438,15 +469,23 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess) e = hipMalloc((void**)&s->arena_base, (size_t)cfg->budget_bytes);
+        // Each slot starts with table buffers for ~16k tiles, so the serving
+        // loop itself allocates only for unusually large batches.
+        const size_t table0 = 256 * 1024;
         for (Slot& sl : s->slots) {
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+            if (e == hipSuccess && (e = hipMalloc(&sl.dev, table0)) == hipSuccess) sl.dev_cap = table0;
+            if (e == hipSuccess && (e = hipHostMalloc(&sl.pinned, table0, hipHostMallocDefault)) == hipSuccess)
+                sl.pinned_cap = table0;
         }
         if (e != hipSuccess) {
             set_error("server create", e);
             for (Slot& sl : s->slots) {
                 if (sl.done) hipEventDestroy(sl.done);
                 if (sl.stream) hipStreamDestroy(sl.stream);
+                if (sl.dev) hipFree(sl.dev);
+                if (sl.pinned) hipHostFree(sl.pinned);
             }
             if (s->arena_base) hipFree(s->arena_base);
             delete s->arena;
@@ -472,6 +511,7 @@ static int submit_locked(tdct_server* s, const tdct_request* req, bool release_o
     q.out_bytes = ob;
     q.submit_us = s->now_us();
     q.release_on_done = release_on_done;
+    s->last_activity_us = q.submit_us;
     s->waiting.push_back(t);
     s->in_flight++;
     s->st.submitted++;

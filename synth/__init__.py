@@ -55,6 +55,8 @@ def _L():
             L.synth_blob_plane.argtypes = [P, i64, i32, i32, u64, i32, i32, i32, f64, i32, i32,
                                            u64, i32, i32]
             L.synth_blob_batch.argtypes = [P, P, P, P, P, P, i32, i32, i32, i32]
+            L.synth_blob_field.argtypes = [P, i32, i32, u64, i32, i32, i32, f64, i32]
+            L.synth_window.argtypes = [P, i32, i32, i32, P, i64, i32, i32, u64, i32, i32]
             _lib = L
     return _lib
 
@@ -175,24 +177,62 @@ class Video420:
         """(Q luma, Q chroma): 64 + s_Y (i + j) and 64 + 2 s_C (i + j)."""
         return qtable(64, int(self.s_luma[f])), qtable(64, int(self.s_chroma[f]), step=2)
 
-    def frame(self, f: int, out=None, threads: int | None = None):
-        """Returns (Y, Cb, Cr) uint8 planes of frame f."""
+    def _plane_params(self, f: int):
         w, h, M = self.w, self.h, self.MARGIN
-        fw, fh = w + 2 * M, h + 2 * M
         ox, oy = int(self.offsets[f][0]), int(self.offsets[f][1])
+        out = []
+        for p in range(3):
+            sc, cw, ch = (1.0, w, h) if p == 0 else (0.5, w // 2, h // 2)
+            px, py = (ox, oy) if p == 0 else (ox // 2, oy // 2)
+            blob_seed = self.seed * 1000003 + (0 if p == 0 else 17)
+            noise_seed = (self.seed << 40) ^ (f << 4) ^ p ^ 0x5851F42D4C957F2D
+            out.append((sc, cw, ch, px, py, blob_seed, noise_seed))
+        return out
+
+    def _fields(self, threads):
+        """The rounded, noise-free field of the whole canvas (luma and the
+        half-resolution chroma view), computed once per sequence."""
+        if getattr(self, "_canvas", None) is None:
+            w, h, M = self.w, self.h, self.MARGIN
+            fw, fh = w + 2 * M, h + 2 * M
+            L = _L()
+            canv = []
+            for p, (sc, cw, ch) in enumerate([(1.0, fw, fh), (0.5, fw // 2, fh // 2)]):
+                a = np.zeros((ch, cw), np.int16)
+                seed = self.seed * 1000003 + (0 if p == 0 else 17)
+                L.synth_blob_field(a.ctypes.data, cw, ch, seed, NBLOBS, fw, fh, sc, _threads(threads))
+                canv.append(a)
+            self._canvas = canv
+        return self._canvas
+
+    def frame(self, f: int, out=None, threads: int | None = None):
+        """Returns (Y, Cb, Cr) uint8 planes of frame f (windows of the canvas
+        field plus fresh noise)."""
+        w, h = self.w, self.h
         if out is None:
             out = (np.zeros((h, w), np.uint8), np.zeros((h // 2, w // 2), np.uint8),
                    np.zeros((h // 2, w // 2), np.uint8))
+        canv = self._fields(threads)
         L = _L()
-        t = _threads(threads)
-        for p, (arr, sc, cw, ch, px, py) in enumerate([
-                (out[0], 1.0, w, h, ox, oy),
-                (out[1], 0.5, w // 2, h // 2, ox // 2, oy // 2),
-                (out[2], 0.5, w // 2, h // 2, ox // 2, oy // 2)]):
-            blob_seed = self.seed * 1000003 + (0 if p == 0 else 17)
-            noise_seed = (self.seed << 40) ^ (f << 4) ^ p ^ 0x5851F42D4C957F2D
+        for p, (sc, cw, ch, px, py, _, noise_seed) in enumerate(self._plane_params(f)):
+            c = canv[0 if p == 0 else 1]
+            arr = out[p]
+            L.synth_window(c.ctypes.data, c.shape[1], px, py, arr.ctypes.data, arr.strides[0], cw, ch,
+                           noise_seed, 4, _threads(threads))
+        return out
+
+    def frame_direct(self, f: int, threads: int | None = None):
+        """The same frame evaluated blob by blob at its own window (slow; used
+        to check the canvas path)."""
+        w, h, M = self.w, self.h, self.MARGIN
+        fw, fh = w + 2 * M, h + 2 * M
+        out = (np.zeros((h, w), np.uint8), np.zeros((h // 2, w // 2), np.uint8),
+               np.zeros((h // 2, w // 2), np.uint8))
+        L = _L()
+        for p, (sc, cw, ch, px, py, blob_seed, noise_seed) in enumerate(self._plane_params(f)):
+            arr = out[p]
             L.synth_blob_plane(arr.ctypes.data, arr.strides[0], cw, ch, blob_seed, NBLOBS, fw, fh,
-                               sc, px, py, noise_seed, 4, t)
+                               sc, px, py, noise_seed, 4, _threads(threads))
         return out
 
 

@@ -182,3 +182,103 @@ void synth_blob_batch(uint8_t* base, const int64_t* off, const int64_t* stride, 
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
     pthread_mutex_destroy(&J.mu);
 }
+
+/* Rounded blob field of a whole canvas (no noise), clipped to [-16, 272]:
+ * clipping this far outside [0, 255] cannot change any final pixel, since the
+ * noise added later is at most 16 in magnitude. Identical values to
+ * synth_blob_plane for the same field, window and scale. */
+typedef struct {
+    int16_t* out;
+    int32_t w, h;
+    const blobs_t* b;
+    const double *gx, *gy;
+    int32_t y0, y1;
+} field_job;
+
+static void* field_worker(void* p) {
+    field_job* j = (field_job*)p;
+    double* acc = (double*)malloc(sizeof(double) * (size_t)j->w + 8);
+    for (int32_t y = j->y0; y < j->y1; ++y) {
+        for (int32_t x = 0; x < j->w; ++x) acc[x] = 0.0;
+        for (int k = 0; k < j->b->nb; ++k) {
+            const double ay = j->b->A[k] * j->gy[(int64_t)k * j->h + y];
+            const double* g = j->gx + (int64_t)k * j->w;
+            for (int32_t x = 0; x < j->w; ++x) acc[x] += ay * g[x];
+        }
+        int16_t* row = j->out + (int64_t)y * j->w;
+        for (int32_t x = 0; x < j->w; ++x) {
+            int32_t v = (int32_t)nearbyint(acc[x]);
+            row[x] = (int16_t)(v < -16 ? -16 : (v > 272 ? 272 : v));
+        }
+    }
+    free(acc);
+    return NULL;
+}
+
+void synth_blob_field(int16_t* out, int32_t w, int32_t h, uint64_t blob_seed, int32_t nblobs,
+                      int32_t fw, int32_t fh, double scale, int32_t nthreads) {
+    blobs_t b;
+    draw_blobs(&b, blob_seed, nblobs, fw, fh, scale);
+    double* gx = (double*)malloc(sizeof(double) * (size_t)b.nb * (size_t)w + 8);
+    double* gy = (double*)malloc(sizeof(double) * (size_t)b.nb * (size_t)h + 8);
+    tables(&b, w, h, 0, 0, gx, gy);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > h) nthreads = h;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    field_job jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        field_job j = {out, w, h, &b, gx, gy, (int32_t)((int64_t)h * t / nthreads),
+                       (int32_t)((int64_t)h * (t + 1) / nthreads)};
+        jobs[t] = j;
+    }
+    for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, field_worker, &jobs[t]);
+    field_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(gx);
+    free(gy);
+}
+
+/* Window (ox, oy) of a precomputed field plus per-pixel noise. */
+typedef struct {
+    const int16_t* field;
+    int32_t fw;
+    int32_t ox, oy;
+    uint8_t* out;
+    int64_t stride;
+    int32_t w;
+    uint64_t noise_seed;
+    int32_t amp;
+    int32_t y0, y1;
+} window_job;
+
+static void* window_worker(void* p) {
+    window_job* j = (window_job*)p;
+    for (int32_t y = j->y0; y < j->y1; ++y) {
+        const int16_t* src = j->field + (int64_t)(y + j->oy) * j->fw + j->ox;
+        uint8_t* row = j->out + (int64_t)y * j->stride;
+        for (int32_t x = 0; x < j->w; ++x) {
+            int32_t v = src[x] + noise_at(j->noise_seed, (uint64_t)y * (uint64_t)j->w + x, j->amp);
+            row[x] = (uint8_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
+        }
+    }
+    return NULL;
+}
+
+void synth_window(const int16_t* field, int32_t fw, int32_t ox, int32_t oy, uint8_t* out,
+                  int64_t stride, int32_t w, int32_t h, uint64_t noise_seed, int32_t amp,
+                  int32_t nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > h) nthreads = h;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    window_job jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        window_job j = {field, fw, ox, oy, out, stride, w, noise_seed, amp,
+                        (int32_t)((int64_t)h * t / nthreads), (int32_t)((int64_t)h * (t + 1) / nthreads)};
+        jobs[t] = j;
+    }
+    for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, window_worker, &jobs[t]);
+    window_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+}

@@ -84,7 +84,20 @@ void hc_shifts(int32_t s[64]) {
 // kernels compute it.
 void hc_quant(int32_t Q, int32_t s, int32_t y0, int32_t n, int32_t* out) {
     const float r = tdct::quant_recip(Q, s, true);
-    for (int32_t k = 0; k < n; ++k) out[k] = tdct::quant_f32(y0 + k, r);
+    for (int32_t k = 0; k < n; ++k) out[k] = tdct::quant_int(y0 + k, r);
+}
+
+// The int8 path's saturation on the raw bits and the int16 path's low half:
+// out8[k] = the byte the encoder stores, out16[k] = the halfword it stores.
+void hc_quant_lanes(int32_t Q, int32_t s, int32_t y0, int32_t n, int8_t* out8, int16_t* out16) {
+    const float r = tdct::quant_recip(Q, s, true);
+    for (int32_t k = 0; k < n; ++k) {
+        uint32_t b = tdct::quant_bits(y0 + k, r);
+        uint32_t c = b < tdct::kRoundMagicBits - 128u ? tdct::kRoundMagicBits - 128u
+                   : (b > tdct::kRoundMagicBits + 127u ? tdct::kRoundMagicBits + 127u : b);
+        out8[k] = (int8_t)(uint8_t)(c & 0xffu);
+        out16[k] = (int16_t)(uint16_t)(b & 0xffffu);
+    }
 }
 
 }  // extern "C"

@@ -184,3 +184,32 @@ def test_server_rejects_bad_requests(tdct):
                 tdct.tdct_server_submit(s, r)
     finally:
         tdct.tdct_server_destroy(s)
+
+
+def test_fake_server_shutdown_with_unreleased_outputs_does_not_hang(tdct):
+    """The second request can never be admitted (the first output is held by
+    the client); destroying the server fails it instead of waiting forever."""
+    import threading
+    s = tdct.tdct_server_create(tdct.server_cfg(64 * 64 * 2, streams=1, max_batch=1, fake_device_us=50))
+    t1 = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 64, 64))
+    assert tdct.tdct_server_wait(s, t1).status == tdct.TDCT_OK
+    t2 = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 64, 64))
+    time.sleep(0.01)
+    assert tdct.tdct_server_poll(s, t2).status == tdct.TDCT_EBUSY  # still waiting for memory
+    th = threading.Thread(target=tdct.tdct_server_destroy, args=(s,))
+    th.start()
+    th.join(timeout=10)
+    assert not th.is_alive()
+
+
+def test_fake_server_pixel_cap_limits_batches(tdct):
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 26, streams=1, max_batch=16, max_wait_us=20000,
+                                                fake_device_us=100, max_batch_px=2 * 64 * 64))
+    try:
+        tickets = [tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 64, 64)) for _ in range(6)]
+        big = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 256, 256))
+        tdct.tdct_server_drain(s)
+        assert {tdct.tdct_server_poll(s, t).batch_size for t in tickets} == {2}
+        assert tdct.tdct_server_poll(s, big).batch_size == 1  # larger than the cap: alone
+    finally:
+        tdct.tdct_server_destroy(s)

@@ -220,3 +220,22 @@ def test_error_codes(tdct):
     with pytest.raises(tdct.TdctError):
         tdct.tdct_quantise(p, 8, 9, 8, Q, 64, p)
     sync()
+
+
+def test_stream_probes_move_the_bytes(tdct):
+    import torch
+    units = 4096 + 17
+    a = torch.randint(0, 256, (2 * units * 16,), dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    tdct.tdct_stream_probe(tdct.PROBE_COPY, a, b, units)
+    sync()
+    assert torch.equal(b[:units * 16], a[:units * 16]) and (b[units * 16:] == 0).all()
+    tdct.tdct_stream_probe(tdct.PROBE_R1W2, a, b, units)
+    sync()
+    av = a[:units * 16]
+    assert torch.equal(b[:units * 16], av) and torch.equal(b[units * 16:], av)
+    tdct.tdct_stream_probe(tdct.PROBE_R2W1, a, b, units)
+    sync()
+    assert torch.equal(b[:units * 16], a[:units * 16] ^ a[units * 16:])
+    with pytest.raises(tdct.TdctError):
+        tdct.tdct_stream_probe(9, a, b, units)

@@ -31,6 +31,7 @@ def hc():
     L.hc_zigzag.argtypes = [P]
     L.hc_shifts.argtypes = [P]
     L.hc_quant.argtypes = [ctypes.c_int32] * 4 + [P]
+    L.hc_quant_lanes.argtypes = [ctypes.c_int32] * 4 + [P, P]
     return L
 
 
@@ -122,3 +123,19 @@ def test_float_quantiser_is_exact_on_the_whole_encoder_domain(hc, oracle_mod):
                 bad.append((s, Q, int(W[k]), int(out[k]), int(exp[k])))
                 break
     assert not bad, bad[:5]
+
+
+def test_quantiser_lane_forms_store_the_right_bits(hc, oracle_mod):
+    """The stored int16 halfword and the saturated int8 byte, taken straight
+    from the float's bits, equal the rounded quotient (clamped for int8)."""
+    rng = np.random.default_rng(31)
+    for Q in [1, 2, 3, 63, 64, 65, 113, 4095] + rng.integers(1, 4096, 40).tolist():
+        for s in range(5):
+            lim = 8192 >> s
+            y = np.arange(-lim, lim + 1, dtype=np.int64)
+            o8 = np.zeros(y.size, np.int8)
+            o16 = np.zeros(y.size, np.int16)
+            hc.hc_quant_lanes(int(Q), s, -lim, y.size, o8.ctypes.data, o16.ctypes.data)
+            exp = oracle_mod.round_div_array(y << s, int(Q))
+            assert np.array_equal(o16.astype(np.int64), exp)
+            assert np.array_equal(o8.astype(np.int64), np.clip(exp, -128, 127))
