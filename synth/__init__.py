@@ -68,14 +68,29 @@ def _threads(n=None) -> int:
 
 
 def plane(w: int, h: int, seed: int, noise: int = 8, stride: int | None = None,
-          out: np.ndarray | None = None, threads: int | None = None) -> np.ndarray:
+          out: np.ndarray | None = None, threads: int | None = None,
+          nblobs: int = NBLOBS) -> np.ndarray:
     """One w x h blob-field image as uint8 [h, stride] (columns >= w are 0)."""
     stride = w if stride is None else stride
     if out is None:
         out = np.zeros((h, stride), np.uint8)
     assert out.dtype == np.uint8 and out.flags.c_contiguous and out.shape[1] >= w
-    _L().synth_blob_plane(out.ctypes.data, out.strides[0], w, h, seed, NBLOBS, w, h, 1.0, 0, 0,
+    _L().synth_blob_plane(out.ctypes.data, out.strides[0], w, h, seed, nblobs, w, h, 1.0, 0, 0,
                           seed ^ 0xA5A5A5A55A5A5A5A, noise, _threads(threads))
+    return out
+
+
+def textured(w: int, h: int, seed: int, stride: int | None = None) -> np.ndarray:
+    """A test image that exercises every coefficient and the whole pixel range
+    at any size: half a two-blob field plus half a horizontal ramp over
+    [0, 255], under strong noise (+-80), clipped. (The 20-blob recipe
+    saturates small images to a constant.)"""
+    stride = w if stride is None else stride
+    base = plane(w, h, seed, noise=0, nblobs=2).astype(np.int64)
+    ramp = (np.arange(w, dtype=np.int64) * 255 // max(1, w - 1))[None, :]
+    noise = np.random.default_rng([seed, 99]).integers(-80, 81, size=(h, w))
+    out = np.zeros((h, stride), np.uint8)
+    out[:, :w] = np.clip(base // 2 + ramp // 2 + noise, 0, 255)
     return out
 
 

@@ -42,7 +42,7 @@ class Ragged:
         for k, (w, h) in enumerate(sizes):
             op = ops[k % len(ops)]
             stride = w + (8 * (k % 3)) + (3 if k % 7 == 3 else 0)
-            img = synth.plane(w, h, 500 + k, stride=stride)
+            img = synth.textured(w, h, 500 + k, stride=stride)
             qt = k % len(self.qtabs)
             keep = [64, 10, 25, 1][k % 4]
             nblk = (w // 8) * (h // 8)

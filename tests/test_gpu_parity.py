@@ -61,7 +61,7 @@ SIZES = [(8, 8), (16, 8), (24, 16), (40, 24), (136, 72), (1024, 64), (520, 48), 
 @pytest.mark.parametrize("w,h", SIZES)
 def test_encode_matches_oracle(tdct, w, h):
     rng = np.random.default_rng(w * 131 + h)
-    img = synth.plane(w, h, 100 + w + h)
+    img = synth.textured(w, h, 100 + w + h)
     for Q, keep in [(synth.qtable(1, 3), 64), (_rand_q(rng), 64), (np.ones(64, np.uint16), 10),
                     (_rand_q(rng, 1, 40), 1), (_rand_q(rng, 1, 9), 37)]:
         got = _encode(tdct, img, Q, keep)
@@ -83,7 +83,7 @@ def test_decode_matches_oracle_on_arbitrary_int16(tdct, w, h):
 
 @pytest.mark.parametrize("w,h", [(8, 8), (136, 72), (512, 512), (24, 40)])
 def test_encoder_output_decodes_like_oracle(tdct, w, h):
-    img = synth.plane(w, h, 7 + w)
+    img = synth.textured(w, h, 7 + w)
     Q = synth.qtable(1, 4)
     q = _encode(tdct, img, Q)
     rec = _decode(tdct, q, Q, w, h)
@@ -92,7 +92,7 @@ def test_encoder_output_decodes_like_oracle(tdct, w, h):
 
 
 def test_unit_Q_round_trip_is_identity_on_gpu(tdct):
-    img = synth.plane(256, 64, 77)
+    img = synth.textured(256, 64, 77)
     one = np.ones(64, np.uint16)
     rec = _decode(tdct, _encode(tdct, img, one), one, 256, 64)
     assert np.array_equal(rec, img)
@@ -101,7 +101,7 @@ def test_unit_Q_round_trip_is_identity_on_gpu(tdct):
 @pytest.mark.parametrize("stride,offset", [(64, 0), (72, 0), (80, 0), (67, 0), (64, 3), (96, 8)])
 def test_strides_and_alignment(tdct, stride, offset):
     w, h = 48, 24
-    img = synth.plane(w, h, 31, stride=stride)
+    img = synth.textured(w, h, 31, stride=stride)
     Q = synth.qtable(1, 2)
     got = _encode(tdct, img, Q, w=w, offset=offset)
     ref = O.quantise(img, Q, 64, w=w)
@@ -113,7 +113,7 @@ def test_strides_and_alignment(tdct, stride, offset):
 def test_roundtrip_kernel(tdct):
     for (w, h), keep, with_q in [((136, 72), 64, True), ((512, 64), 10, False), ((24, 16), 25, True),
                                  ((8, 8), 1, True)]:
-        img = synth.plane(w, h, 5 + w)
+        img = synth.textured(w, h, 5 + w)
         Q = synth.qtable(1, 6)
         _, sp = plane_dev(img)
         nblk = (w // 8) * (h // 8)
@@ -130,7 +130,7 @@ def test_roundtrip_kernel(tdct):
 
 def test_roundtrip_in_place(tdct):
     w, h = 64, 32
-    img = synth.plane(w, h, 8)
+    img = synth.textured(w, h, 8)
     Q = synth.qtable(1, 1)
     d, p = plane_dev(img)
     tdct.tdct_roundtrip(p, w, w, h, Q, 64, None, p, w)
@@ -162,7 +162,7 @@ def test_forward_int32_and_psnr_single_image(tdct):
 
 @pytest.mark.parametrize("w,h", [(3840, 16), (1920, 8), (24, 24), (8, 8)])
 def test_i8_zigzag_encoder(tdct, w, h):
-    img = synth.plane(w, h, 44 + w)
+    img = synth.textured(w, h, 44 + w)
     for Q in (synth.qtable(64, 3), synth.qtable(64, 5, step=2), synth.qtable(1, 1)):
         _, sp = plane_dev(img)
         nblk = (w // 8) * (h // 8)

@@ -42,7 +42,7 @@ class Workload:
     def __init__(self, tdct, rate=3000.0, seconds=0.12, seed=55):
         import torch
         rng = np.random.default_rng(seed)
-        self.planes = [synth.plane(POOL_SIDE, POOL_SIDE, 7000 + k) for k in range(2)]
+        self.planes = [synth.textured(POOL_SIDE, POOL_SIDE, 7000 + k) for k in range(2)]
         self.coefs = [rng.integers(-300, 301, size=((POOL_SIDE // 8) ** 2, 64)).astype(np.int16)
                       for _ in range(2)]
         self.dplanes = [torch.from_numpy(p).cuda() for p in self.planes]
