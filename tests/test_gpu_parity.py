@@ -239,3 +239,39 @@ def test_stream_probes_move_the_bytes(tdct):
     assert torch.equal(b[:units * 16], a[:units * 16] ^ a[units * 16:])
     with pytest.raises(tdct.TdctError):
         tdct.tdct_stream_probe(9, a, b, units)
+
+
+def _sampled_blocks_match(img_dev, w, h, q_dev, rec_dev, Q, nsample, seed):
+    """Checks sampled blocks (plus the four corners) of a large encode/decode
+    against the oracle, each recomputed from its own 8x8 pixels."""
+    rng = np.random.default_rng(seed)
+    nbx, nby = w // 8, h // 8
+    picks = [(0, 0), (nbx - 1, 0), (0, nby - 1), (nbx - 1, nby - 1)]
+    picks += list(zip(rng.integers(0, nbx, nsample).tolist(), rng.integers(0, nby, nsample).tolist()))
+    Q = np.asarray(Q)
+    for bx, by in picks:
+        blk = img_dev[8 * by:8 * by + 8, 8 * bx:8 * bx + 8].cpu().numpy()
+        q_ref, rec_ref = O.roundtrip(np.ascontiguousarray(blk), Q)
+        b = by * nbx + bx
+        assert np.array_equal(q_dev[b].cpu().numpy(), q_ref[0]), (bx, by)
+        assert np.array_equal(rec_dev[8 * by:8 * by + 8, 8 * bx:8 * bx + 8].cpu().numpy(), rec_ref), (bx, by)
+
+
+@pytest.mark.parametrize("w,h", [(65536, 64), (64, 65536), (8, 8192), (8192, 8), (65536, 65536)])
+def test_maximum_sides(tdct, w, h):
+    """Sides up to the 65536 limit; the last case holds 2^32 pixels, so byte
+    offsets of pixels and coefficients pass 2^32."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(w * 7 + h)
+    img = torch.randint(0, 256, (h, w), dtype=torch.uint8, device="cuda", generator=g)
+    nblk = (w // 8) * (h // 8)
+    q = torch.empty((nblk, 64), dtype=torch.int16, device="cuda")
+    rec = torch.empty((h, w), dtype=torch.uint8, device="cuda")
+    Q = synth.qtable(1, 2)
+    tdct.tdct_quantise(img, w, w, h, Q, 64, q)
+    tdct.tdct_inverse(q, Q, w, h, rec, w)
+    sync()
+    _sampled_blocks_match(img, w, h, q, rec, Q, 300, w + h)
+    del img, q, rec
+    torch.cuda.empty_cache()
