@@ -292,6 +292,74 @@ def video_leg(tdct, torch, stream, frames=256, reps=5):
             "speedup": round(per_s / graph_s, 2), "bytes_per_sample": 2}
 
 
+def dct2_matrix():
+    """Orthonormal 8-point DCT-II (the exact transform the paper compares with)."""
+    import numpy as np
+    k = np.arange(8)[:, None]
+    n = np.arange(8)[None, :]
+    M = np.cos((2 * n + 1) * k * np.pi / 16) * np.sqrt(2 / 8)
+    M[0, :] = np.sqrt(1 / 8)
+    return M
+
+
+def quality_leg(tdct, torch, stream, n_images=45, side=512, rs=range(2, 46)):
+    """The paper's image-compression experiment (zonal coding, Section 3) on a
+    synthetic stand-in for its 45-image set: for every r, the integer codec
+    (Q = 1, zonal keep r) runs on the GPU with an exact SSE per image; the
+    exact DCT-II with the same zonal rule, rounding and clamp runs on the host
+    in float64. Reported: mean PSNR, PSNR of the mean MSE, and the absolute
+    percentage error of the average MSE relative to the DCT (Fig. 2 methodology)."""
+    import numpy as np
+
+    import synth
+    rs = list(rs)
+    one = np.ones(64, np.uint16)
+    imgs = [synth.plane(side, side, 100 + i) for i in range(n_images)]
+    src = torch.from_numpy(np.stack(imgs)).cuda()
+    dst = torch.empty_like(src)
+    sse = torch.zeros((n_images, len(rs)), dtype=torch.int64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(n_images):
+        for k, r in enumerate(rs):
+            tdct.tdct_roundtrip(src[i], side, side, side, one, r, None, dst[i], side, stream)
+            tdct.tdct_sse(src[i], side, dst[i], side, side, side, sse[i, k].data_ptr(), stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gpu_ms = e0.elapsed_time(e1)
+    sse_ours = sse.cpu().numpy().astype(np.float64)
+    # exact DCT reference on the host (float64), same zonal rule
+    C = dct2_matrix()
+    order = []
+    for d in range(15):  # JPEG zigzag, as in the codec
+        cells = [(i, d - i) for i in range(8) if 0 <= d - i < 8]
+        order += cells if d % 2 else cells[::-1]
+    rank = np.empty((8, 8), np.int64)
+    for t, (i, j) in enumerate(order):
+        rank[i, j] = t
+    sse_dct = np.zeros((n_images, len(rs)))
+    for i, img in enumerate(imgs):
+        X = img.reshape(side // 8, 8, side // 8, 8).transpose(0, 2, 1, 3).astype(np.float64) - 128
+        Y = np.einsum("ab,xybc,dc->xyad", C, X, C)
+        for k, r in enumerate(rs):
+            Z = np.einsum("ba,xybc,cd->xyad", C, Y * (rank < r), C)
+            rec = np.clip(np.floor(Z + 0.5) + 128, 0, 255)
+            sse_dct[i, k] = ((rec - X - 128) ** 2).sum()
+    npx = side * side
+    rows = []
+    for k, r in enumerate(rs):
+        mse_o = sse_ours[:, k] / npx
+        mse_d = sse_dct[:, k] / npx
+        psnr_o = np.where(mse_o > 0, 10 * np.log10(255.0 ** 2 / np.maximum(mse_o, 1e-300)), np.inf)
+        rows.append({"r": r, "compression_pct": round(100 * (64 - r) / 64, 4),
+                     "psnr_mean": round(float(np.mean(psnr_o)), 3),
+                     "psnr_of_mean_mse": round(float(10 * np.log10(255.0 ** 2 / mse_o.mean())), 3),
+                     "psnr_dct_of_mean_mse": round(float(10 * np.log10(255.0 ** 2 / mse_d.mean())), 3),
+                     "ape_mse_pct": round(float(abs(mse_o.mean() - mse_d.mean()) / mse_d.mean() * 100), 3)})
+    return {"images": n_images, "side": side, "gpu_ms": round(gpu_ms, 2),
+            "gpu_launches": 2 * n_images * len(rs), "table": rows}
+
+
 def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
     """Poisson encode/decode requests with device-resident payloads, served by
     continuous batching and by one plain launch per request."""
@@ -379,6 +447,8 @@ def main():
                     help="fixed launch shapes instead of autotuning: "
                          "'WPG,GPC,TW:WPG,GPC,TW' for the encoder and the decoder")
     ap.add_argument("--serving-seconds", type=float, default=4.0)
+    ap.add_argument("--quality", action="store_true",
+                    help="also run the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -484,6 +554,9 @@ def main():
         torch.cuda.empty_cache()
         log("serving leg...")
         result["serving"] = serving_leg(tdct, torch, args.serving_seconds)
+    if args.quality:
+        log("quality leg...")
+        result["quality"] = quality_leg(tdct, torch, stream)
     print(json.dumps(result), flush=True)
 
 

@@ -159,7 +159,7 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
         fill_desc(im.op, im.src, im.src_stride, im.w, im.h, im.coef, im.dst, im.dst_stride, qi,
                   im.op == TDCT_OP_ROUNDTRIP && im.coef != nullptr, &p->imgs[i]);
         p->blk_off[i + 1] = p->blk_off[i] + p->imgs[i].nblk;
-        p->ops |= 1 << im.op;
+        p->ops |= 1 << p->imgs[i].op;
         p->pixels += (int64_t)im.w * im.h;
     }
     if (p->qcs.empty()) {
@@ -362,7 +362,7 @@ int tdct_run_per_image(const tdct_image_desc* imgs, int32_t n, const tdct_qtable
         ImgDesc d;
         fill_desc(im.op, im.src, im.src_stride, im.w, im.h, im.coef, im.dst, im.dst_stride, 0,
                   im.op == TDCT_OP_ROUNDTRIP && im.coef != nullptr, &d);
-        if ((st = launch_plain_op(im.op, d, qc, (hipStream_t)stream))) return st;
+        if ((st = launch_plain_op(d.op, d, qc, (hipStream_t)stream))) return st;
     }
     return TDCT_OK;
 }

@@ -159,7 +159,9 @@ struct QConst {
     int32_t Q[64];
 };
 
-enum : int32_t { OP_ENCODE = 0, OP_DECODE = 1, OP_ROUNDTRIP = 2, OP_ENCODE_I8ZZ = 3, OP_FORWARD = 4 };
+enum : int32_t { OP_ENCODE = 0, OP_DECODE = 1, OP_ROUNDTRIP = 2, OP_ENCODE_I8ZZ = 3, OP_FORWARD = 4,
+                 // internal: a round trip whose coefficients never leave the registers
+                 OP_ROUNDTRIP_NC = 5 };
 
 // Flags describing which load/store widths an image allows.
 enum : int32_t {

@@ -173,18 +173,9 @@ __device__ __forceinline__ int64_t block_offset(int64_t stride, uint32_t nbx, ui
 
 // ---- decoder core ----------------------------------------------------------
 
-// Dequantise + inverse transform of one block whose int16 coefficients sit in
-// 32 dwords (natural order, two per dword), producing 8 rows of 8 pixels.
-template <class QC>
-__device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC& qc,
-                                             uint32_t (&px)[8][2]) {
-    int W[64];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        // |q| <= 2^15 and Q <= 4095 fit the 24-bit multiplier exactly.
-        W[2 * k] = __mul24((int)(short)(qp[k] & 0xffffu), qc.Q[2 * k]);
-        W[2 * k + 1] = __mul24((int)qp[k] >> 16, qc.Q[2 * k + 1]);
-    }
+// Inverse transform of one block of dequantised coefficients W'_ij (natural
+// order) into 8 rows of 8 pixels: floor((S + 32) / 64) + 128, clamped.
+__device__ __forceinline__ void reconstruct(int (&W)[64], uint32_t (&px)[8][2]) {
     // +32 rounds floor((S + 32) / 64); +8192 = 64 * 128 undoes the level
     // shift. Column 0 of T^t is all ones, so adding both to W'_00 adds them
     // to every S_rc.
@@ -198,6 +189,21 @@ __device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC&
         px[r][0] = pack8(p[0], p[1], p[2], p[3]);
         px[r][1] = pack8(p[4], p[5], p[6], p[7]);
     }
+}
+
+// Dequantise + inverse transform of one block whose int16 coefficients sit in
+// 32 dwords (natural order, two per dword), producing 8 rows of 8 pixels.
+template <class QC>
+__device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC& qc,
+                                             uint32_t (&px)[8][2]) {
+    int W[64];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        // |q| <= 2^15 and Q <= 4095 fit the 24-bit multiplier exactly.
+        W[2 * k] = __mul24((int)(short)(qp[k] & 0xffffu), qc.Q[2 * k]);
+        W[2 * k + 1] = __mul24((int)qp[k] >> 16, qc.Q[2 * k + 1]);
+    }
+    reconstruct(W, px);
 }
 
 // ---- encoder tile ------------------------------------------------------------
@@ -291,6 +297,30 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
         v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 4;
         stage_out<4>(wl, ma, 4 * na, out, lane);
         stage_out<4>(wl, mb, 4 * nb, out + 256, lane);
+    } else if constexpr (OP == OP_ROUNDTRIP_NC) {
+        // Encode and decode without storing coefficients. The rounding
+        // float's low 24 bits are 0x400000 + q (|q| < 2^22), so one 24-bit
+        // multiply-add gives W' = q Q directly: (0x400000 + q) Q - (Q << 22),
+        // exact modulo 2^32 and |q Q| < 2^31.
+        uint32_t px[8][2];
+        if (va) {
+            int W[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k)
+                W[k] = (int)(__umul24(quant_bits(v[k].x, qc.r[k]), (uint32_t)qc.Q[k]) -
+                             ((uint32_t)qc.Q[k] << 22));
+            reconstruct(W, px);
+            store_rows8(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+        }
+        if (vb) {
+            int W[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k)
+                W[k] = (int)(__umul24(quant_bits(v[k].y, qc.r[k]), (uint32_t)qc.Q[k]) -
+                             ((uint32_t)qc.Q[k] << 22));
+            reconstruct(W, px);
+            store_rows8(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
+        }
     } else {
         // OP_ENCODE / OP_ROUNDTRIP: int16 coefficients, natural order.
         uint32_t qa[32], qb[32];
@@ -426,6 +456,10 @@ __global__ __launch_bounds__(512) void batch_kernel(const Tile* __restrict__ til
                     if constexpr ((OPS >> OP_ENCODE_I8ZZ) & 1)
                         run_tile<OP_ENCODE_I8ZZ>(d, qc, tl.first_lo, tl.count, lane, wl);
                     break;
+                case OP_ROUNDTRIP_NC:
+                    if constexpr ((OPS >> OP_ROUNDTRIP_NC) & 1)
+                        run_tile<OP_ROUNDTRIP_NC>(d, qc, tl.first_lo, tl.count, lane, wl);
+                    break;
                 default:
                     if constexpr ((OPS >> OP_FORWARD) & 1)
                         run_tile<OP_FORWARD>(d, qc, tl.first_lo, tl.count, lane, wl);
@@ -550,6 +584,7 @@ int launch_plain_op(int op, const ImgDesc& d, const QConst& qc, hipStream_t stre
         case OP_ROUNDTRIP: return launch_plain<OP_ROUNDTRIP>(d, qc, stream);
         case OP_ENCODE_I8ZZ: return launch_plain<OP_ENCODE_I8ZZ>(d, qc, stream);
         case OP_FORWARD: return launch_plain<OP_FORWARD>(d, qc, stream);
+        case OP_ROUNDTRIP_NC: return launch_plain<OP_ROUNDTRIP_NC>(d, qc, stream);
     }
     return TDCT_EINVAL;
 }
@@ -581,8 +616,9 @@ int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint
                  int ops, const tdct_tune& tune, int num_cus, hipStream_t stream) {
     if (ntiles == 0) return TDCT_OK;
     constexpr int E = 1 << OP_ENCODE, D = 1 << OP_DECODE, R = 1 << OP_ROUNDTRIP,
-                  Z = 1 << OP_ENCODE_I8ZZ, F = 1 << OP_FORWARD;
+                  Z = 1 << OP_ENCODE_I8ZZ, F = 1 << OP_FORWARD, N = 1 << OP_ROUNDTRIP_NC;
     switch (ops) {
+        case N: return launch_batch_ops<N>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
         case E: return launch_batch_ops<E>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
         case D: return launch_batch_ops<D>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
         case R: return launch_batch_ops<R>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
@@ -590,7 +626,8 @@ int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint
         case F: return launch_batch_ops<F>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
         case E | D: return launch_batch_ops<E | D>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
         default:
-            return launch_batch_ops<E | D | R | Z | F>(tiles, imgs, qcs, ntiles, tune, num_cus, stream);
+            return launch_batch_ops<E | D | R | Z | F | N>(tiles, imgs, qcs, ntiles, tune, num_cus,
+                                                           stream);
     }
 }
 
@@ -603,7 +640,7 @@ int fill_desc(int op, const uint8_t* src, int64_t src_stride, int32_t w, int32_t
     d->dst_stride = dst_stride;
     d->nbx = w / 8;
     d->nblk = (int64_t)(w / 8) * (h / 8);
-    d->op = op;
+    d->op = (op == OP_ROUNDTRIP && !write_coef) ? OP_ROUNDTRIP_NC : op;
     d->qidx = qidx;
     d->flags = image_flags(*d) | (write_coef ? F_COEF : 0);
     return TDCT_OK;
@@ -669,7 +706,7 @@ int tdct_roundtrip(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
               q_or_null != nullptr, &d);
     QConst qc;
     make_qconst(Q, keep, &qc);
-    return launch_plain_op(OP_ROUNDTRIP, d, qc, (hipStream_t)stream);
+    return launch_plain_op(d.op, d, qc, (hipStream_t)stream);
 }
 
 int tdct_quantise_i8_zigzag(const uint8_t* src, int64_t src_stride, int32_t w, int32_t h,
