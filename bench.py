@@ -361,8 +361,10 @@ def quality_leg(tdct, torch, stream, n_images=45, side=512, rs=range(2, 46)):
 
 
 def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
-    """Poisson encode/decode requests with device-resident payloads, served by
-    continuous batching and by one plain launch per request."""
+    """Poisson encode/decode requests served by continuous batching and by one
+    plain launch per request, with device-resident payloads; and the same
+    stream with host-resident payloads copied in and out over PCIe
+    (host_io_batched, the PCIe-inclusive rate)."""
     import numpy as np
 
     import synth
@@ -378,6 +380,12 @@ def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
         tdct.tdct_quantise(pool[k], max_side, max_side, max_side, synth.qtable(1, 1 + k), 64, c)
         coefs.append(c)
     torch.cuda.synchronize()
+    # host-resident payloads for the PCIe-inclusive mode: pinned copies of the
+    # pool, and a few pinned output buffers of the largest size reused in turn
+    # (requests in flight may overwrite each other's host copies: timing only)
+    hpool = [p.cpu().pin_memory() for p in pool]
+    hcoefs = [c.cpu().pin_memory() for c in coefs]
+    houts = [torch.empty(2 * max_side * max_side, dtype=torch.uint8).pin_memory() for _ in range(4)]
     out = {}
     for rate in rates:
         tr = synth.serving_trace(rate, seconds, seed=5)
@@ -393,13 +401,24 @@ def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
         arrival = (tr["t"] * 1e6).tolist()
         px = int((tr["w"] * tr["h"]).sum())
         res = {"requests": len(reqs), "mpx_mean": round(px / max(1, len(reqs)) / 1e6, 3)}
-        for mode, batching in (("batched", 1), ("per_request", 0)):
+        hreqs = []
+        for k in range(len(tr["t"])):
+            w, h, s = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k])
+            p, o = k % pool_n, houts[k % len(houts)].data_ptr()
+            if tr["op"][k] == 0:
+                hreqs.append(tdct.request(tdct.OP_ENCODE, w, h, hpool[p].data_ptr(), synth.qtable(1, s),
+                                          keep=64, in_stride=max_side, host_output=o))
+            else:
+                hreqs.append(tdct.request(tdct.OP_DECODE, w, h, hcoefs[p].data_ptr(), synth.qtable(1, s),
+                                          host_output=o))
+        for mode, batching, rq in (("batched", 1, reqs), ("per_request", 0, reqs),
+                                   ("host_io_batched", 1, hreqs)):
             srv = tdct.tdct_server_create(tdct.server_cfg(64 << 30, streams=streams, max_batch=64,
                                                           max_wait_us=0, batching=batching,
                                                           max_batch_px=MAX_BATCH_PX))
             try:
                 t0 = time.perf_counter()
-                _, lat, st = tdct.tdct_server_replay(srv, reqs, arrival)
+                _, lat, st = tdct.tdct_server_replay(srv, rq, arrival)
                 wall = time.perf_counter() - t0
                 stats = tdct.tdct_server_stats(srv)
             finally:

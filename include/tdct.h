@@ -217,15 +217,23 @@ typedef struct {
     int32_t op;      /* TDCT_OP_ENCODE or TDCT_OP_DECODE */
     int32_t w, h;
     int32_t keep;    /* ENCODE only */
-    const void* input; /* device: uint8 plane (ENCODE) or int16 coefficients (DECODE) */
+    const void* input; /* uint8 plane (ENCODE) or int16 coefficients (DECODE); device memory,
+                          or pinned host memory when host_io */
     int64_t in_stride; /* ENCODE: bytes per row */
     tdct_qtable Q;
+    int32_t host_io;   /* 0: device-resident input, output left in the arena.
+                          1: the input is copied host -> device into the arena and the output
+                          device -> host into host_output, on the request's stream, before the
+                          request completes (the arena holds both copies meanwhile) */
+    int32_t reserved;
+    void* host_output; /* host_io: pinned host buffer of the output's size */
 } tdct_request;
 
 typedef struct {
     int32_t status;       /* TDCT_OK done, TDCT_EBUSY pending, < 0 failed */
     int32_t batch_size;   /* requests in the launch that served it */
-    void* output;         /* device, in the arena: int16 [w*h/64][64] or uint8 [h][w] */
+    void* output;         /* device, in the arena: int16 [w*h/64][64] or uint8 [h][w]
+                             (host_io: the caller's host_output) */
     int64_t output_bytes;
     double submit_us;     /* host clock, microseconds since server start */
     double done_us;       /* completion observed on the host */
@@ -257,6 +265,8 @@ int tdct_server_release(tdct_server* s, uint64_t ticket);
 /* Blocks until every submitted request has completed. */
 int tdct_server_drain(tdct_server* s);
 int tdct_server_stats(tdct_server* s, tdct_stats* out);
+/* Text of the last HIP error the scheduler met ("" if none). */
+const char* tdct_server_last_error(tdct_server* s);
 void tdct_server_destroy(tdct_server* s);
 
 /* Open-loop replay: request k is submitted at arrival_us[k] after the call

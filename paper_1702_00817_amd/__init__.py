@@ -77,7 +77,8 @@ class tdct_server_cfg(ctypes.Structure):
 class tdct_request(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
                 ("keep", ctypes.c_int32), ("input", ctypes.c_void_p), ("in_stride", ctypes.c_int64),
-                ("Q", tdct_qtable)]
+                ("Q", tdct_qtable), ("host_io", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("host_output", ctypes.c_void_p)]
 
 
 class tdct_result(ctypes.Structure):
@@ -137,6 +138,8 @@ _lib.tdct_plan_free.argtypes = [_P]
 _lib.tdct_plan_free.restype = None
 _lib.tdct_server_destroy.argtypes = [_P]
 _lib.tdct_server_destroy.restype = None
+_lib.tdct_server_last_error.argtypes = [_P]
+_lib.tdct_server_last_error.restype = ctypes.c_char_p
 
 
 def lib():
@@ -317,12 +320,17 @@ def server_cfg(budget_bytes, streams=4, max_batch=64, max_wait_us=0, batching=1,
     return c
 
 
-def request(op, w, h, inp, Q, keep=64, in_stride=None) -> tdct_request:
+def request(op, w, h, inp, Q, keep=64, in_stride=None, host_output=None) -> tdct_request:
+    """A serving request; with host_output given, input and output are pinned
+    host buffers (host_io)."""
     r = tdct_request()
     r.op, r.w, r.h, r.keep = op, w, h, keep
     r.input = _ptr(inp)
     r.in_stride = w if in_stride is None else in_stride
     r.Q = qtable(Q)
+    if host_output is not None:
+        r.host_io = 1
+        r.host_output = _ptr(host_output)
     return r
 
 
@@ -363,6 +371,10 @@ def tdct_server_stats(server) -> dict:
     s = tdct_stats()
     _check(_lib.tdct_server_stats(server, ctypes.byref(s)), "tdct_server_stats")
     return s.as_dict()
+
+
+def tdct_server_last_error(server) -> str:
+    return _lib.tdct_server_last_error(server).decode()
 
 
 def tdct_server_destroy(server):

@@ -92,7 +92,7 @@ class Arena {
 struct Req {
     tdct_request r{};
     int64_t out_bytes = 0;
-    int64_t arena_off = -1;
+    int64_t arena_off = -1;  // output at arena_off, staged input at arena_off + round(out_bytes)
     double submit_us = 0, done_us = 0;
     int32_t status = TDCT_EBUSY;
     int32_t batch_size = 0;
@@ -153,15 +153,29 @@ int64_t output_bytes(const tdct_request& r) {
     return r.op == TDCT_OP_ENCODE ? 2 * px : px;
 }
 
+// Device staging a host_io request needs for its input (packed rows for a plane).
+int64_t staging_bytes(const tdct_request& r) {
+    if (!r.host_io) return 0;
+    const int64_t px = (int64_t)r.w * r.h;
+    return r.op == TDCT_OP_ENCODE ? px : 2 * px;
+}
+
+// Arena bytes a request holds while it is in the server.
+int64_t reserve_bytes(const tdct_request& r) {
+    int64_t n = (output_bytes(r) + 255) & ~int64_t(255);
+    return n + staging_bytes(r);
+}
+
 int validate_request(const tdct_request& r) {
     if (r.op != TDCT_OP_ENCODE && r.op != TDCT_OP_DECODE) return TDCT_EINVAL;
     if (r.w <= 0 || r.h <= 0 || (r.w & 7) || (r.h & 7) || r.w > TDCT_MAX_SIDE || r.h > TDCT_MAX_SIDE)
         return TDCT_EDIM;
     if (!r.input) return TDCT_EINVAL;
+    if (r.host_io && !r.host_output) return TDCT_EINVAL;
     if (r.op == TDCT_OP_ENCODE) {
         if (r.in_stride < r.w) return TDCT_EINVAL;
         if (r.keep < 1 || r.keep > 64) return TDCT_EINVAL;
-    } else if ((uintptr_t)r.input % 16) {
+    } else if (!r.host_io && (uintptr_t)r.input % 16) {
         return TDCT_EINVAL;
     }
     return validate_q(&r.Q);
@@ -201,8 +215,25 @@ int ensure_capacity(tdct_server* s, Slot& sl, size_t bytes) {
 struct BatchItem {
     uint64_t ticket;
     tdct_request r;
-    void* out;
+    void* out;      // device output in the arena
+    void* staged;   // host_io: device copy of the input in the arena
 };
+
+// host_io: host -> device copy of a request's input into its staging.
+int stage_input(const BatchItem& it, hipStream_t st) {
+    const tdct_request& r = it.r;
+    hipError_t e;
+    if (r.op == TDCT_OP_ENCODE)
+        e = hipMemcpy2DAsync(it.staged, (size_t)r.w, r.input, (size_t)r.in_stride, (size_t)r.w,
+                             (size_t)r.h, hipMemcpyHostToDevice, st);
+    else
+        e = hipMemcpyAsync(it.staged, r.input, (size_t)staging_bytes(r), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        set_error("server input copy", e);
+        return TDCT_EDEVICE;
+    }
+    return TDCT_OK;
+}
 
 // Builds tables for the batch and launches it on the slot. No lock held.
 int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>& items) {
@@ -216,12 +247,18 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
             QConst qc;
             make_qconst(&r.Q, r.op == TDCT_OP_ENCODE ? r.keep : 64, &qc);
             ImgDesc d;
+            const void* in = r.host_io ? it.staged : r.input;
+            const int64_t in_stride = r.host_io ? r.w : r.in_stride;
+            if (r.host_io) {
+                int st = stage_input(it, sl.stream);
+                if (st) return st;
+            }
             if (r.op == TDCT_OP_ENCODE)
-                fill_desc(OP_ENCODE, (const uint8_t*)r.input, r.in_stride, r.w, r.h, it.out, nullptr,
-                          0, 0, true, &d);
+                fill_desc(OP_ENCODE, (const uint8_t*)in, in_stride, r.w, r.h, it.out, nullptr, 0, 0,
+                          true, &d);
             else
-                fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(r.input),
-                          (uint8_t*)it.out, r.w, 0, false, &d);
+                fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(in), (uint8_t*)it.out,
+                          r.w, 0, false, &d);
             int st = launch_plain_op(d.op, d, qc, sl.stream);
             if (st) return st;
         }
@@ -233,11 +270,17 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
         for (int i = 0; i < n; ++i) {
             const tdct_request& r = items[i].r;
             make_qconst(&r.Q, r.op == TDCT_OP_ENCODE ? r.keep : 64, &qcs[i]);
+            const void* in = r.host_io ? items[i].staged : r.input;
+            const int64_t in_stride = r.host_io ? r.w : r.in_stride;
+            if (r.host_io) {
+                int st = stage_input(items[i], sl.stream);
+                if (st) return st;
+            }
             if (r.op == TDCT_OP_ENCODE)
-                fill_desc(OP_ENCODE, (const uint8_t*)r.input, r.in_stride, r.w, r.h, items[i].out,
-                          nullptr, 0, i, true, &imgs[i]);
+                fill_desc(OP_ENCODE, (const uint8_t*)in, in_stride, r.w, r.h, items[i].out, nullptr,
+                          0, i, true, &imgs[i]);
             else
-                fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(r.input),
+                fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(in),
                           (uint8_t*)items[i].out, r.w, i, false, &imgs[i]);
             ops |= 1 << imgs[i].op;
             const int tb = tile_blocks(imgs[i].op);
@@ -271,6 +314,15 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
                           s->num_cus, sl.stream);
         if (st) return st;
     }
+    for (const BatchItem& it : items) {
+        if (!it.r.host_io) continue;
+        hipError_t e = hipMemcpyAsync(it.r.host_output, it.out, (size_t)output_bytes(it.r),
+                                      hipMemcpyDeviceToHost, sl.stream);
+        if (e != hipSuccess) {
+            set_error("server output copy", e);
+            return TDCT_EDEVICE;
+        }
+    }
     hipError_t e = hipEventRecord(sl.done, sl.stream);
     if (e != hipSuccess) {
         set_error("server event", e);
@@ -294,8 +346,8 @@ void finish_request(tdct_server* s, uint64_t t, int status, int batch_size, doub
     } else {
         s->st.failed++;
     }
-    if ((q.release_on_done || status != TDCT_OK) && q.arena_off >= 0) {
-        s->arena->release(q.arena_off, q.out_bytes);
+    if ((q.release_on_done || q.r.host_io || status != TDCT_OK) && q.arena_off >= 0) {
+        s->arena->release(q.arena_off, reserve_bytes(q.r));
         q.arena_off = -1;
     }
 }
@@ -343,7 +395,7 @@ void scheduler(tdct_server* s) {
         // 2. admission, FIFO
         while (!s->waiting.empty()) {
             Req& q = s->reqs[s->waiting.front()];
-            const int64_t off = s->arena->alloc(q.out_bytes);
+            const int64_t off = s->arena->alloc(reserve_bytes(q.r));
             if (off < 0) {
                 // Shutting down with nothing left in flight: the memory this
                 // request waits for is held by outputs the client never
@@ -385,7 +437,9 @@ void scheduler(tdct_server* s) {
                     break;
                 batch_px += px;
                 s->admitted.pop_front();
-                items.push_back({t, q.r, s->arena_base + q.arena_off});
+                char* base = s->arena_base + q.arena_off;
+                items.push_back({t, q.r, base,
+                                 q.r.host_io ? base + Arena::round(q.out_bytes) : nullptr});
                 sl.tickets.push_back(t);
             }
             sl.busy = true;
@@ -501,7 +555,7 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
 static int submit_locked(tdct_server* s, const tdct_request* req, bool release_on_done,
                          uint64_t* ticket) {
     const int64_t ob = output_bytes(*req);
-    if (Arena::round(ob) > s->arena->size()) {
+    if (Arena::round(reserve_bytes(*req)) > s->arena->size()) {
         s->st.rejected++;
         return TDCT_ENOMEM;
     }
@@ -535,7 +589,9 @@ int tdct_server_submit(tdct_server* s, const tdct_request* req, uint64_t* ticket
 static void fill_result(const tdct_server* s, const Req& q, tdct_result* out) {
     out->status = q.status;
     out->batch_size = q.batch_size;
-    out->output = (q.status == TDCT_OK && q.arena_off >= 0) ? s->arena_base + q.arena_off : nullptr;
+    out->output = q.status != TDCT_OK ? nullptr
+                  : q.r.host_io ? q.r.host_output
+                  : (q.arena_off >= 0 ? s->arena_base + q.arena_off : nullptr);
     out->output_bytes = q.out_bytes;
     out->submit_us = q.submit_us;
     out->done_us = q.done_us;
@@ -571,7 +627,7 @@ int tdct_server_release(tdct_server* s, uint64_t ticket) {
         auto it = s->reqs.find(ticket);
         if (it == s->reqs.end()) return TDCT_ENOTFOUND;
         if (it->second.status == TDCT_EBUSY) return TDCT_EBUSY;
-        if (it->second.arena_off >= 0) s->arena->release(it->second.arena_off, it->second.out_bytes);
+        if (it->second.arena_off >= 0) s->arena->release(it->second.arena_off, reserve_bytes(it->second.r));
         s->reqs.erase(it);
     }
     s->wake.notify_one();
@@ -610,6 +666,12 @@ int tdct_server_stats(tdct_server* s, tdct_stats* out) {
     return TDCT_OK;
 }
 
+const char* tdct_server_last_error(tdct_server* s) {
+    if (!s) return "";
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->err;
+}
+
 void tdct_server_destroy(tdct_server* s) {
     if (!s) return;
     {
@@ -642,7 +704,7 @@ int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* a
     for (int32_t k = 0; k < n; ++k) {
         int st = validate_request(reqs[k]);
         if (st) return st;
-        kept += Arena::round(output_bytes(reqs[k]));
+        if (!reqs[k].host_io) kept += Arena::round(reserve_bytes(reqs[k]));
     }
     // Kept outputs are released only after this call returns, so they must
     // all fit at once, or admission would wait forever.

@@ -213,3 +213,18 @@ def test_fake_server_pixel_cap_limits_batches(tdct):
         assert tdct.tdct_server_poll(s, big).batch_size == 1  # larger than the cap: alone
     finally:
         tdct.tdct_server_destroy(s)
+
+
+def test_host_io_request_needs_a_host_output(tdct):
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 20, fake_device_us=10))
+    try:
+        r = tdct.request(tdct.OP_DECODE, 8, 8, 0x1008, np.ones(64))
+        r.host_io = 1  # no host_output
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_submit(s, r)
+        assert e.value.status == tdct.TDCT_EINVAL
+        ok = tdct.request(tdct.OP_DECODE, 8, 8, 0x1008, np.ones(64), host_output=0x2000)
+        t = tdct.tdct_server_submit(s, ok)  # unaligned host input is fine: it is staged
+        assert tdct.tdct_server_wait(s, t).output == 0x2000
+    finally:
+        tdct.tdct_server_destroy(s)

@@ -146,3 +146,36 @@ def test_tight_budget_queues_instead_of_failing(tdct):
         assert e.value.status == tdct.TDCT_ENOMEM
     finally:
         tdct.tdct_server_destroy(srv)
+
+
+def test_host_payloads_equal_device_resident_results(tdct):
+    """host_io requests: pinned host input, copied in, coded, copied back to a
+    pinned host buffer; the bytes equal the device-resident path and the oracle."""
+    import torch
+    W = Workload(tdct, rate=10000.0, seconds=0.01, seed=57)
+    n = len(W.reqs)
+    hplanes = [torch.from_numpy(p).pin_memory() for p in W.planes]
+    hcoefs = [torch.from_numpy(c).pin_memory() for c in W.coefs]
+    outs, reqs = [], []
+    for k, m in enumerate(W.meta):
+        o = torch.zeros(m["nbytes"], dtype=torch.uint8).pin_memory()
+        outs.append(o)
+        if m["op"] == 0:
+            reqs.append(tdct.request(tdct.OP_ENCODE, m["w"], m["h"], hplanes[m["p"]].data_ptr(), m["Q"],
+                                     keep=m["keep"], in_stride=POOL_SIDE, host_output=o.data_ptr()))
+        else:
+            reqs.append(tdct.request(tdct.OP_DECODE, m["w"], m["h"], hcoefs[m["p"]].data_ptr(), m["Q"],
+                                     host_output=o.data_ptr()))
+    srv = tdct.tdct_server_create(tdct.server_cfg(64 << 20, streams=4, max_batch=16, max_wait_us=200))
+    try:
+        tickets, lat, st = tdct.tdct_server_replay(srv, reqs, W.arrival)
+        assert all(s_ == tdct.TDCT_OK for s_ in st)
+        stats = tdct.tdct_server_stats(srv)
+        assert stats["arena_bytes_in_use"] == 0  # staging and outputs went back
+    finally:
+        tdct.tdct_server_destroy(srv)
+    dev, _, _ = _serve(tdct, W, tdct.server_cfg(1 << 30, streams=4, max_batch=16, batching=1))
+    for k in range(n):
+        assert np.array_equal(outs[k].numpy(), dev[k]), k
+    for k in range(0, n, 7):
+        assert np.array_equal(outs[k].numpy(), W.expected(k)), k
