@@ -42,7 +42,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("tdct_kernels.hip", "tdct_device.hpp"):
+    for f in ("tdct_kernels.hip", "tdct_tiles.hpp", "tdct_device.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1702_00817_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -360,12 +360,20 @@ def quality_leg(tdct, torch, stream, n_images=45, side=512, rs=range(2, 46)):
             "gpu_launches": 2 * n_images * len(rs), "table": rows}
 
 
-def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
-    """Poisson encode/decode requests served by continuous batching and by one
-    plain launch per request, with device-resident payloads; and the same
-    stream with host-resident payloads copied in and out over PCIe
-    (host_io_batched, the PCIe-inclusive rate)."""
+def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4, resident_workers=0,
+                modes=("batched", "per_request", "resident", "host_io_batched")):
+    """Poisson encode/decode requests served by continuous batching, by one
+    plain launch per request and by the resident polling kernel, with
+    device-resident payloads; and the same stream with host-resident payloads
+    copied in and out over PCIe (host_io_batched, the PCIe-inclusive rate)."""
     import numpy as np
+
+    def cfg(mode):
+        if mode == "resident":
+            return tdct.server_cfg(64 << 30, resident=1, resident_workers=resident_workers,
+                                   resident_idle_us=100000)
+        return tdct.server_cfg(64 << 30, streams=streams, max_batch=64, max_wait_us=0,
+                               batching=0 if mode == "per_request" else 1, max_batch_px=MAX_BATCH_PX)
 
     import synth
     max_side = 8192
@@ -411,11 +419,9 @@ def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
             else:
                 hreqs.append(tdct.request(tdct.OP_DECODE, w, h, hcoefs[p].data_ptr(), synth.qtable(1, s),
                                           host_output=o))
-        for mode, batching, rq in (("batched", 1, reqs), ("per_request", 0, reqs),
-                                   ("host_io_batched", 1, hreqs)):
-            srv = tdct.tdct_server_create(tdct.server_cfg(64 << 30, streams=streams, max_batch=64,
-                                                          max_wait_us=0, batching=batching,
-                                                          max_batch_px=MAX_BATCH_PX))
+        for mode in modes:
+            rq = hreqs if mode == "host_io_batched" else reqs
+            srv = tdct.tdct_server_create(cfg(mode))
             try:
                 t0 = time.perf_counter()
                 _, lat, st = tdct.tdct_server_replay(srv, rq, arrival)
@@ -433,10 +439,10 @@ def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
                          "arena_high_water_gb": round(stats["arena_high_water"] / 1e9, 3)}
         if rate == max(rates):
             # capacity: the same requests all arriving at once (closed burst)
-            for mode, batching in (("batched", 1), ("per_request", 0)):
-                srv = tdct.tdct_server_create(tdct.server_cfg(64 << 30, streams=streams, max_batch=64,
-                                                              max_wait_us=0, batching=batching,
-                                                              max_batch_px=MAX_BATCH_PX))
+            for mode in modes:
+                if mode == "host_io_batched":
+                    continue
+                srv = tdct.tdct_server_create(cfg(mode))
                 try:
                     t0 = time.perf_counter()
                     _, lat, st = tdct.tdct_server_replay(srv, reqs, [0.0] * len(reqs))
@@ -449,7 +455,8 @@ def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4):
                                         "failed": int(sum(1 for s_ in st if s_ != 0))}
         out[str(rate)] = res
         log("serving %d req/s: %s" % (rate, json.dumps(res)))
-    return {"seconds_per_rate": seconds, "streams": streams, "budget_gb": 64, "rates": out}
+    return {"seconds_per_rate": seconds, "streams": streams, "budget_gb": 64,
+            "resident_workers": resident_workers or "one per CU", "rates": out}
 
 
 def main():

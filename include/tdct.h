@@ -211,6 +211,28 @@ typedef struct {
                                batch "completes" this many microseconds after launch
                                (exercises admission and batching on a CPU) */
     int32_t fake_fail_every; /* fake device only: every n-th batch fails (0 = never) */
+    /* Resident mode (resident = 1): no launch per batch. Requests go into a
+     * queue in host-coherent pinned memory that a resident kernel polls; its
+     * front wave copies each request to the device and cuts it into tiles,
+     * its worker waves claim tiles from a device-side ring and code them, and
+     * the wave that finishes a request's last tile raises the request's done
+     * flag in host memory, which the scheduler polls. The kernel exits after
+     * resident_idle_us without a new request (and after one second in any
+     * case) and is relaunched by the next one. streams, max_batch,
+     * max_wait_us, batching, max_batch_px and tune are unused; host_io
+     * requests are refused (TDCT_EINVAL). With fake_device_us > 0 a host
+     * thread plays the kernel's part of the protocol. */
+    int32_t resident;
+    int32_t resident_workers; /* worker waves (0: one per compute unit; clamped to what
+                                 fits on the device at once) */
+    int32_t resident_idle_us; /* 0: 20000 */
+    int32_t resident_jobs;    /* queue slots, rounded up to a power of two (0: 1024,
+                                 at most 65536); a request holds its slot until done */
+    int32_t resident_tiles;   /* tile-ring slots, rounded up to a power of two (0: 2^21,
+                                 at most 2^24); a request with more tiles than this
+                                 (blocks / 128 encoding, blocks / 64 decoding) is
+                                 refused with TDCT_ENOMEM */
+    int32_t resident_reserved;
 } tdct_server_cfg;
 
 typedef struct {
@@ -231,7 +253,8 @@ typedef struct {
 
 typedef struct {
     int32_t status;       /* TDCT_OK done, TDCT_EBUSY pending, < 0 failed */
-    int32_t batch_size;   /* requests in the launch that served it */
+    int32_t batch_size;   /* requests in the launch that served it (resident mode: requests
+                             in the queue when it was published, itself included) */
     void* output;         /* device, in the arena: int16 [w*h/64][64] or uint8 [h][w]
                              (host_io: the caller's host_output) */
     int64_t output_bytes;
@@ -241,7 +264,7 @@ typedef struct {
 
 typedef struct {
     int64_t submitted, completed, failed, rejected;
-    int64_t batches;
+    int64_t batches;      /* launches (resident mode: launches of the resident kernel) */
     int64_t pixels_done;
     int64_t arena_bytes_in_use, arena_high_water;
     double busy_us;       /* wall time with at least one batch in flight */

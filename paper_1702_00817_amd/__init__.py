@@ -71,7 +71,10 @@ class tdct_server_cfg(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
                 ("batching", ctypes.c_int32), ("max_batch_px", ctypes.c_int64), ("tune", tdct_tune),
-                ("fake_device_us", ctypes.c_int32), ("fake_fail_every", ctypes.c_int32)]
+                ("fake_device_us", ctypes.c_int32), ("fake_fail_every", ctypes.c_int32),
+                ("resident", ctypes.c_int32), ("resident_workers", ctypes.c_int32),
+                ("resident_idle_us", ctypes.c_int32), ("resident_jobs", ctypes.c_int32),
+                ("resident_tiles", ctypes.c_int32), ("resident_reserved", ctypes.c_int32)]
 
 
 class tdct_request(ctypes.Structure):
@@ -310,13 +313,16 @@ def tdct_run_per_image(descs, qtabs, stream=None):
 # ---- serving form ------------------------------------------------------------
 
 def server_cfg(budget_bytes, streams=4, max_batch=64, max_wait_us=0, batching=1, tune=None,
-               fake_device_us=0, fake_fail_every=0, max_batch_px=0) -> tdct_server_cfg:
+               fake_device_us=0, fake_fail_every=0, max_batch_px=0, resident=0, resident_workers=0,
+               resident_idle_us=0, resident_jobs=0, resident_tiles=0) -> tdct_server_cfg:
     c = tdct_server_cfg()
     c.budget_bytes, c.streams, c.max_batch = budget_bytes, streams, max_batch
     c.max_wait_us, c.batching, c.max_batch_px = max_wait_us, batching, max_batch_px
     if tune:
         c.tune = tdct_tune(**tune)
     c.fake_device_us, c.fake_fail_every = fake_device_us, fake_fail_every
+    c.resident, c.resident_workers, c.resident_idle_us = resident, resident_workers, resident_idle_us
+    c.resident_jobs, c.resident_tiles = resident_jobs, resident_tiles
     return c
 
 

@@ -17,11 +17,15 @@ LIB = os.path.join(PKG, "libtdct.so")
 HOSTCHECK_SRC = os.path.join(ROOT, "tests", "hostcheck.cpp")
 HOSTCHECK_LIB = os.path.join(ROOT, "tests", "libhostcheck.so")
 
-SOURCES = ["tdct_kernels.hip", "tdct_probe.hip", "tdct_batch.cpp", "tdct_server.cpp"]
+SOURCES = ["tdct_kernels.hip", "tdct_probe.hip", "tdct_resident.hip", "tdct_batch.cpp",
+           "tdct_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The resident kernel's atomics take a lane-0-only operand; a DPP scan folds
+# them into one atomic per wave in a few dozen instructions.
+PER_SOURCE = {"tdct_resident.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP"]}
 
 
 def _run(cmd, verbose):
@@ -44,7 +48,7 @@ def build_lib(verbose: bool = False) -> str:
         path = os.path.join(CSRC, src)
         obj = os.path.join(bdir, src + ".o")
         lang = ["-x", "hip"] + DEVICE if src.endswith(".hip") else ["-D__HIP_PLATFORM_AMD__"]
-        _run([HIPCC] + COMMON + lang + ["-c", path, "-o", obj], verbose)
+        _run([HIPCC] + COMMON + lang + PER_SOURCE.get(src, []) + ["-c", path, "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs +

@@ -25,4 +25,10 @@ int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint
 // LDS bytes per workgroup of the batch kernel for an op set and launch shape.
 uint32_t batch_lds_bytes(int ops, int waves_per_group);
 
+struct ResidentArgs;
+// Workgroups of the resident kernel that fit on the device at once.
+int resident_capacity(int num_cus, int* groups);
+// One front wave plus `workers` worker waves.
+int launch_resident(const ResidentArgs& a, int workers, hipStream_t stream);
+
 }  // namespace tdct

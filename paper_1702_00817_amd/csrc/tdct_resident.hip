@@ -1,0 +1,248 @@
+// Resident serving kernel: a grid that stays on the GPU and takes requests
+// from a queue in host-coherent memory (layout and protocol in
+// tdct_resident.hpp).
+//
+// Workgroup 0 is the front wave: it polls the host's published count, copies
+// each new job into device memory, cuts it into work items of one or more
+// tiles, fills the job's entries of the item ring and then publishes the
+// items with a release store. Every other workgroup is one worker wave: it
+// takes a ticket for the next item, waits until that item is published,
+// copies the item's job into its LDS, runs the encoder or decoder tiles of
+// the item (the same per-wave code as the batch kernel) and counts the item
+// off (a wave that keeps getting items of one job counts them off together,
+// before it waits, changes job or holds 8); the wave that finishes a job's
+// last item writes the job's done flag into host memory with a system-scope
+// release.
+//
+// Every wave has an exit that it always reaches: the front wave leaves when
+// the host sets the stop bit, after idle_ticks without a new job or after
+// life_ticks; workers leave once the front wave has left and their ticket
+// (below) is beyond the last published item, or after twice life_ticks. The
+// host relaunches the kernel when work arrives and no launch is live; the
+// state in device memory carries over between launches.
+//
+// Synchronisation uses only vector memory operations: scoped atomic loads,
+// stores and fetch-adds, plus fences; polling loads are relaxed, so an idle
+// wave issues no cache maintenance. Job data
+// written inside the kernel is read with lane-indexed loads and kept in LDS.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tdct.h"
+#include "tdct_device.hpp"
+#include "tdct_internal.hpp"
+#include "tdct_resident.hpp"
+#include "tdct_tiles.hpp"
+
+namespace tdct {
+namespace {
+
+__device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t ticks() { return (uint64_t)wall_clock64(); }
+
+// Back-off between polls: `n` sleeps of 16 x 64 clocks each.
+__device__ __forceinline__ void nap(uint32_t n) {
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(16);
+}
+
+// Reads a trivially copyable record from LDS into wave-uniform registers.
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized record");
+    T out;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(p);
+    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = __builtin_amdgcn_readfirstlane(s[i]);
+    return out;
+}
+
+// Control flow in the protocol code below is kept wave-uniform: every lane
+// issues the same loads and stores (same address, one request), and atomics
+// take a lane-0-only operand instead of sitting behind a lane test. A
+// `lane == 0` branch around an atomic would let the compiler route the other
+// lanes around it and back into a polling loop whose exit only lane 0
+// decides.
+
+__device__ void front_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0) {
+    uint64_t taken = first_lane64(__hip_atomic_load(&a.st->taken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    uint64_t items = first_lane64(__hip_atomic_load(&a.st->items_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t jmask = a.ring_jobs - 1, imask = a.ring_items - 1;
+    // lanes 36..63 all handle the job's last 16-byte chunk (same value, same place)
+    const uint32_t k = lane < (uint32_t)kJobChunks ? lane : (uint32_t)kJobChunks - 1;
+    uint64_t last = t0;
+    while (true) {
+        const uint64_t ctrl = first_lane64(__hip_atomic_load(a.ctrl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+        const uint64_t now = ticks();
+        if ((ctrl & kCtrlStop) || now - t0 > a.life_ticks) break;
+        if (taken < (ctrl & ~kCtrlStop)) {
+            const uint32_t slot = (uint32_t)taken & jmask;
+            v4u c = reinterpret_cast<const v4u*>(a.ring + slot)[k];
+            // last chunk: base (x, y), ntiles (z), done_value (w)
+            const uint32_t ntiles = (uint32_t)__shfl((int)c.z, kJobChunks - 1);
+            const uint32_t per = item_tiles(ntiles, a.workers);
+            uint32_t nitems = (ntiles + per - 1) / per;
+            nitems = nitems > a.ring_items ? a.ring_items : nitems;
+            const bool last_chunk = k == (uint32_t)kJobChunks - 1;
+            c.x = last_chunk ? (uint32_t)items : c.x;
+            c.y = last_chunk ? (uint32_t)(items >> 32) : c.y;
+            reinterpret_cast<v4u*>(a.jobs + slot)[k] = c;
+            a.remaining[slot] = nitems;
+            for (uint32_t i = lane; i < nitems; i += 64) a.item_slot[(uint32_t)(items + i) & imask] = slot;
+            // job copy, count and item entries before the items become visible
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            taken += 1;
+            items += nitems;
+            __hip_atomic_store(&a.st->taken, taken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.st->items_pub, items, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            last = now;
+            continue;
+        }
+        if (now - last > a.idle_ticks) break;
+        nap(1);
+    }
+    __hip_atomic_store(&a.st->stop_epoch, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The job's pointers came through LDS; rebuilding them as global-space
+// pointers lets the tile code use global instead of flat instructions.
+template <class T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+    typedef __attribute__((address_space(1))) T GT;
+    return (T*)(GT*)(uintptr_t)p;
+}
+
+// 1 once item t is published, 2 when the wave should leave holding t;
+// `pub` receives the published count seen.
+__device__ __forceinline__ uint32_t ticket_state(const ResidentArgs& a, uint64_t t, uint64_t t0, uint64_t& pub) {
+    pub = first_lane64(__hip_atomic_load(&a.st->items_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (pub > t) return 1;
+    const uint32_t stop = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&a.st->stop_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (stop != a.epoch && ticks() - t0 <= 2 * a.life_ticks) return 0;
+    // the front wave's last publication precedes its exit
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    pub = first_lane64(__hip_atomic_load(&a.st->items_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    return pub > t ? 1 : 2;
+}
+
+// Items a wave may code before it counts them off (while they belong to the
+// same job and the next item is already published).
+constexpr uint32_t kMaxPendingItems = 8;
+
+__device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v4u* wl, v4u* jl) {
+    const uint32_t imask = a.ring_items - 1;
+    const uint32_t k = lane < (uint32_t)kJobChunks ? lane : (uint32_t)kJobChunks - 1;
+    // Items coded and not yet counted off, all of the job in pend_slot.
+    uint32_t pend_slot = 0, pend_items = 0, pend_done = 0;
+    auto count_off = [&]() {
+        if (pend_items == 0) return;
+        // this wave's outputs before the count; the job's before its flag
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t left = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_fetch_add(&a.remaining[pend_slot], lane == 0 ? 0u - pend_items : 0u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT));
+        if (left == pend_items) {
+            // every other wave's outputs of the job (released before their
+            // counts), then all of them out to the host
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            __hip_atomic_store(&a.done[pend_slot], pend_done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        pend_items = 0;
+    };
+    while (true) {
+        // A ticket is the index of the next work item this wave codes; taking
+        // one always succeeds, and the wave then waits for that item to be
+        // published. A wave that leaves holding an unpublished ticket loses
+        // it: before a relaunch the host rewinds the cursor to the published
+        // count, which is where the first lost ticket starts.
+        const uint64_t t = first_lane64(__hip_atomic_fetch_add(&a.st->cursor, lane == 0 ? 1ull : 0ull,
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        uint64_t pub;
+        uint32_t state = ticket_state(a, t, t0, pub);
+        if (state != 1) {
+            count_off();  // nothing else to do meanwhile
+            uint32_t backoff = 1;
+            while (state == 0) {
+                // waves far down the queue poll less often
+                const uint64_t ahead = t - pub;
+                const uint32_t far = ahead > 32 * 32 ? 32u : (uint32_t)(ahead / 32);
+                nap(backoff > far ? backoff : far);
+                backoff = backoff < 8 ? 2 * backoff : 8;
+                state = ticket_state(a, t, t0, pub);
+            }
+            if (state == 2) break;
+        }
+        // item t's entry, its job copy and count were released before the
+        // publication that covered t
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const uint32_t slot = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                  &a.item_slot[(uint32_t)t & imask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+                              (a.ring_jobs - 1);
+        if (slot != pend_slot) count_off();
+        jl[k] = reinterpret_cast<const v4u*>(a.jobs + slot)[k];
+        lds_fence();
+        const ResidentJob* J = reinterpret_cast<const ResidentJob*>(jl);
+        ImgDesc d = uniform_copy(&J->d);
+        d.src = global_ptr(d.src);
+        d.dst = global_ptr(d.dst);
+        d.coef = global_ptr(d.coef);
+        const uint64_t base = first_lane64(J->base);
+        const uint32_t ntiles = __builtin_amdgcn_readfirstlane(J->ntiles);
+        const uint32_t per = item_tiles(ntiles, a.workers);
+        const uint32_t tb = (uint32_t)tile_blocks(d.op);
+        const uint64_t tile0 = (t - base) * per;
+        const uint64_t tile1 = min(tile0 + per, (uint64_t)ntiles);
+        for (uint64_t tile = tile0; tile < tile1; ++tile) {
+            const uint64_t first = tile * tb;
+            if (first >= (uint64_t)d.nblk) break;
+            const uint32_t count = (uint32_t)min((uint64_t)tb, (uint64_t)d.nblk - first);
+            if (d.op == OP_ENCODE)
+                run_tile<OP_ENCODE>(d, J->qc, (uint32_t)first, count, lane, wl);
+            else if (d.op == OP_DECODE)
+                run_tile<OP_DECODE>(d, J->qc, (uint32_t)first, count, lane, wl);
+        }
+        pend_slot = slot;
+        pend_done = __builtin_amdgcn_readfirstlane(J->done_value);
+        if (++pend_items >= kMaxPendingItems) count_off();
+    }
+    count_off();
+}
+
+__global__ __launch_bounds__(64) void resident_kernel(const ResidentArgs a) {
+    extern __shared__ v4u lds[];
+    const uint32_t lane = threadIdx.x;
+    const uint64_t t0 = ticks();
+    if (blockIdx.x == 0)
+        front_wave(a, lane, t0);
+    else
+        worker_wave(a, lane, t0, lds, lds + kResidentStageBytes / 16);
+}
+
+}  // namespace
+
+// Workgroups of the resident kernel that fit on the device at once.
+int resident_capacity(int num_cus, int* groups) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_kernel, 64,
+                                                                kResidentLdsBytes);
+    if (e != hipSuccess) {
+        set_error("resident kernel occupancy", e);
+        return TDCT_EDEVICE;
+    }
+    *groups = per_cu * num_cus;
+    return TDCT_OK;
+}
+
+int launch_resident(const ResidentArgs& a, int workers, hipStream_t stream) {
+    hipLaunchKernelGGL(resident_kernel, dim3(1 + workers), dim3(64), kResidentLdsBytes, stream, a);
+    return check_launch("resident kernel launch");
+}
+
+}  // namespace tdct

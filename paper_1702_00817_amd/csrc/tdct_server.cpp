@@ -15,6 +15,12 @@
 // others run are admitted and launched as memory and slots free up, and their
 // kernels overlap on the device (continuous batching). With batching = 0 the
 // same loop launches each request on its own (the per-image baseline).
+//
+// Resident mode replaces step 3: admitted requests are written into a queue
+// in host-coherent memory that a resident kernel polls (tdct_resident.hip),
+// and step 1 reads the per-request done flags that kernel writes back. The
+// scheduler launches the kernel only when requests are live and no launch
+// is on the device (it exits by itself when idle).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -28,12 +34,14 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "tdct.h"
 #include "tdct_internal.hpp"
+#include "tdct_resident.hpp"
 
 using namespace tdct;
 
@@ -113,6 +121,37 @@ struct Slot {
     size_t pinned_cap = 0;
 };
 
+// Resident mode: the queue in host-coherent memory, the kernel's state in
+// device memory, and the requests published and not yet retired.
+struct Resident {
+    uint32_t ring_jobs = 0, ring_tiles = 0;
+    int workers = 0;
+    double idle_us = 0;
+    hipStream_t stream = nullptr;
+    void* host = nullptr;  // control word | job ring | done flags
+    uint64_t* ctrl = nullptr;
+    ResidentJob* ring = nullptr;
+    uint32_t* done = nullptr;
+    void* dev = nullptr;  // state | remaining | job copies | tile ring
+    ResidentArgs args{};
+    uint32_t epoch = 0;
+    bool running = false;  // a launch may still be on the device
+    uint64_t next_seq = 0, next_tile = 0;
+    double stop_us = -1;  // when shutdown found requests still live
+    struct Live {
+        uint64_t ticket, seq, tile_base;
+        uint32_t ntiles;
+        int32_t queued;  // requests live when it was published, itself included
+        bool finished;
+    };
+    std::deque<Live> live;  // publication order
+    // Fake device: a host thread plays the kernel's part of the protocol.
+    std::thread fake;
+    std::atomic<bool> fake_live{false};
+    uint64_t fake_taken = 0, fake_tiles = 0;
+    std::vector<uint32_t> fake_tile_slot;
+};
+
 }  // namespace
 
 struct tdct_server {
@@ -128,6 +167,7 @@ struct tdct_server {
     std::deque<uint64_t> admitted;  // output reserved, not launched
     std::unordered_map<uint64_t, Req> reqs;
     std::vector<Slot> slots;
+    Resident res;
     std::thread worker;
     bool stop = false;
     uint64_t next_ticket = 1;
@@ -179,6 +219,18 @@ int validate_request(const tdct_request& r) {
         return TDCT_EINVAL;
     }
     return validate_q(&r.Q);
+}
+
+// Tiles the resident kernel cuts a request into.
+int64_t request_tiles(const tdct_request& r) {
+    const int64_t nblk = ((int64_t)r.w / 8) * ((int64_t)r.h / 8);
+    const int64_t tb = r.op == TDCT_OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
+    return (nblk + tb - 1) / tb;
+}
+
+int validate_for(const tdct_server* s, const tdct_request& r) {
+    if (s->cfg.resident && r.host_io) return TDCT_EINVAL;
+    return validate_request(r);
 }
 
 // Grows a slot's device and pinned buffers to `bytes` (rarely: capacity
@@ -356,6 +408,307 @@ void finish_request(tdct_server* s, uint64_t t, int status, int batch_size, doub
 // sleeps on its condition variable.
 constexpr double kSpinUs = 2000.0;
 
+// ---- resident mode -------------------------------------------------------
+
+void fake_error(tdct_server* s, const char* what) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->err[0]) snprintf(s->err, sizeof(s->err), "fake resident device: %s", what);
+}
+
+// The kernel's side of the protocol on the host, for tests without a GPU:
+// takes published jobs in order, fills the tile ring, and raises each job's
+// done flag fake_device_us x (1 + ntiles % 4) after taking it, so jobs finish
+// out of order. Before raising a flag it checks that the job's queue slot and
+// tile entries still belong to it (the host must not reuse them earlier).
+void fake_resident(tdct_server* s) {
+    Resident& R = s->res;
+    struct Pending {
+        uint32_t slot, ntiles, value;
+        uint64_t base;
+        double due;
+    };
+    std::vector<Pending> pend;
+    double last = s->now_us();
+    const uint32_t jmask = R.ring_jobs - 1, tmask = R.ring_tiles - 1;
+    while (true) {
+        const uint64_t ctrl = __atomic_load_n(R.ctrl, __ATOMIC_ACQUIRE);
+        const double t = s->now_us();
+        while (R.fake_taken < (ctrl & ~kCtrlStop)) {
+            const uint32_t slot = (uint32_t)R.fake_taken & jmask;
+            const ResidentJob& J = R.ring[slot];
+            if (J.base != R.fake_tiles) fake_error(s, "tile count before the job differs from the tiles taken");
+            for (uint32_t k = 0; k < J.ntiles; ++k) R.fake_tile_slot[(uint32_t)(R.fake_tiles + k) & tmask] = slot;
+            pend.push_back({slot, J.ntiles, J.done_value, R.fake_tiles,
+                            t + s->cfg.fake_device_us * (1.0 + (double)(J.ntiles % 4))});
+            R.fake_tiles += J.ntiles;
+            R.fake_taken++;
+            last = t;
+        }
+        for (size_t i = 0; i < pend.size();) {
+            const Pending& p = pend[i];
+            if (p.due > t) {
+                ++i;
+                continue;
+            }
+            if (R.ring[p.slot].done_value != p.value) fake_error(s, "queue slot reused before its job finished");
+            for (uint32_t k = 0; k < p.ntiles; ++k)
+                if (R.fake_tile_slot[(uint32_t)(p.base + k) & tmask] != p.slot) {
+                    fake_error(s, "tile entry overwritten before its job finished");
+                    break;
+                }
+            __atomic_store_n(&R.done[p.slot], p.value, __ATOMIC_RELEASE);
+            pend.erase(pend.begin() + (ptrdiff_t)i);
+        }
+        if (pend.empty() && ((ctrl & kCtrlStop) || t - last > R.idle_us)) break;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    R.fake_live.store(false, std::memory_order_release);
+}
+
+int resident_init(tdct_server* s) {
+    Resident& R = s->res;
+    const tdct_server_cfg& c = s->cfg;
+    auto pow2 = [](int64_t v, int64_t dflt, int64_t hi) {
+        if (v <= 0) v = dflt;
+        v = std::min(v, hi);
+        int64_t p = 1;
+        while (p < v) p <<= 1;
+        return (uint32_t)p;
+    };
+    R.ring_jobs = pow2(c.resident_jobs, 1024, 65536);
+    R.ring_tiles = pow2(c.resident_tiles, 1 << 21, 1 << 24);
+    R.idle_us = c.resident_idle_us > 0 ? c.resident_idle_us : 20000;
+    const size_t ring_off = 256, done_off = ring_off + (size_t)R.ring_jobs * sizeof(ResidentJob);
+    const size_t host_bytes = (done_off + (size_t)R.ring_jobs * 4 + 255) & ~size_t(255);
+    if (s->fake) {
+        R.host = aligned_alloc(256, host_bytes);
+        if (!R.host) return TDCT_ENOMEM;
+        memset(R.host, 0, host_bytes);
+        R.fake_tile_slot.assign(R.ring_tiles, 0xffffffffu);
+    } else {
+        hipError_t e = hipHostMalloc(&R.host, host_bytes, hipHostMallocCoherent | hipHostMallocMapped);
+        if (e != hipSuccess) {
+            R.host = nullptr;
+            set_error("resident queue", e);
+            return TDCT_ENOMEM;
+        }
+        memset(R.host, 0, host_bytes);
+    }
+    char* h = (char*)R.host;
+    R.ctrl = (uint64_t*)h;
+    R.ring = (ResidentJob*)(h + ring_off);
+    R.done = (uint32_t*)(h + done_off);
+    if (s->fake) return TDCT_OK;
+
+    int dev = 0, khz = 0, groups = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess || khz <= 0) {
+        set_error("resident clock rate", e);
+        return TDCT_EDEVICE;
+    }
+    int st = resident_capacity(s->num_cus, &groups);
+    if (st) return st;
+    R.workers = c.resident_workers > 0 ? c.resident_workers : s->num_cus;
+    R.workers = std::min(R.workers, groups - 1);
+    if (R.workers < 1) return TDCT_EDEVICE;
+    void* hdev = nullptr;
+    e = hipHostGetDevicePointer(&hdev, R.host, 0);
+    const size_t rem_off = sizeof(ResidentState);
+    const size_t jobs_off = (rem_off + (size_t)R.ring_jobs * 4 + 255) & ~size_t(255);
+    const size_t slot_off = jobs_off + (size_t)R.ring_jobs * sizeof(ResidentJob);
+    const size_t dev_bytes = slot_off + (size_t)R.ring_tiles * 4;
+    if (e == hipSuccess) e = hipMalloc(&R.dev, dev_bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking);
+    // cleared on the kernel's own stream and waited for: the stream does not
+    // order itself after the null stream
+    if (e == hipSuccess) e = hipMemsetAsync(R.dev, 0, dev_bytes, R.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(R.stream);
+    if (e != hipSuccess) {
+        set_error("resident setup", e);
+        return e == hipErrorOutOfMemory ? TDCT_ENOMEM : TDCT_EDEVICE;
+    }
+    char* hd = (char*)hdev;
+    char* d = (char*)R.dev;
+    ResidentArgs& a = R.args;
+    a.ctrl = (const uint64_t*)hd;
+    a.ring = (const ResidentJob*)(hd + ring_off);
+    a.done = (uint32_t*)(hd + done_off);
+    a.st = (ResidentState*)d;
+    a.remaining = (uint32_t*)(d + rem_off);
+    a.jobs = (ResidentJob*)(d + jobs_off);
+    a.item_slot = (uint32_t*)(d + slot_off);
+    a.ring_jobs = R.ring_jobs;
+    a.ring_items = R.ring_tiles;
+    a.workers = (uint32_t)R.workers;
+    a.idle_ticks = (uint64_t)(R.idle_us * (double)khz / 1000.0);
+    a.life_ticks = (uint64_t)khz * 1000;  // one second
+    return TDCT_OK;
+}
+
+void resident_free(tdct_server* s) {
+    Resident& R = s->res;
+    if (s->fake) {
+        if (R.fake.joinable()) R.fake.join();
+        free(R.host);
+    } else {
+        if (R.stream) {
+            hipStreamSynchronize(R.stream);
+            hipStreamDestroy(R.stream);
+        }
+        if (R.dev) hipFree(R.dev);
+        if (R.host) hipHostFree(R.host);
+    }
+    R.host = R.dev = nullptr;
+    R.stream = nullptr;
+}
+
+// Starts the kernel (or its host stand-in). Lock held.
+int resident_launch(tdct_server* s) {
+    Resident& R = s->res;
+    R.epoch++;
+    s->batches++;
+    if (s->fake) {
+        if (R.fake.joinable()) R.fake.join();  // its loop has ended: fake_live was false
+        R.fake_live.store(true, std::memory_order_release);
+        R.fake = std::thread(fake_resident, s);
+    } else {
+        R.args.epoch = R.epoch;
+        if (R.epoch > 1) {
+            // Tickets the last launch's workers left with are beyond its last
+            // published work item; start handing out tickets from there again.
+            hipError_t e = hipMemcpyAsync(&R.args.st->cursor, &R.args.st->items_pub, sizeof(uint64_t),
+                                          hipMemcpyDeviceToDevice, R.stream);
+            if (e != hipSuccess) {
+                set_error("resident cursor rewind", e);
+                return TDCT_EDEVICE;
+            }
+        }
+        int st = launch_resident(R.args, R.workers, R.stream);
+        if (st) return st;
+    }
+    R.running = true;
+    return TDCT_OK;
+}
+
+// Step 1 in resident mode: notices the end of a launch, retires requests
+// whose done flag is up. Returns whether requests are still live. Lock held.
+bool resident_completions(tdct_server* s, double now) {
+    Resident& R = s->res;
+    if (R.running) {
+        bool ended;
+        int status = TDCT_OK;
+        if (s->fake) {
+            ended = !R.fake_live.load(std::memory_order_acquire);
+        } else {
+            const hipError_t e = hipStreamQuery(R.stream);
+            ended = e != hipErrorNotReady;
+            if (ended && e != hipSuccess) {
+                set_error("resident kernel", e);
+                memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
+                status = TDCT_EDEVICE;
+            }
+        }
+        if (ended) {
+            R.running = false;
+            if (status) {
+                for (Resident::Live& L : R.live)
+                    if (!L.finished) {
+                        finish_request(s, L.ticket, status, L.queued, now);
+                        L.finished = true;
+                    }
+                s->done.notify_all();
+            }
+        }
+    }
+    bool any = false;
+    for (Resident::Live& L : R.live) {
+        if (L.finished) continue;
+        const uint32_t f = __atomic_load_n(&R.done[(uint32_t)L.seq & (R.ring_jobs - 1)], __ATOMIC_ACQUIRE);
+        if (f == (uint32_t)(L.seq + 1)) {
+            finish_request(s, L.ticket, TDCT_OK, L.queued, now);
+            L.finished = true;
+            any = true;
+        }
+    }
+    if (any) {
+        s->last_activity_us = now;
+        s->done.notify_all();
+    }
+    while (!R.live.empty() && R.live.front().finished) R.live.pop_front();
+    return !R.live.empty();
+}
+
+// Requests still live this long after shutdown began are failed, so that a
+// fault in the queue protocol cannot hang the server's destruction.
+constexpr double kResidentStopUs = 5e6;
+
+void resident_shutdown_watchdog(tdct_server* s, double now) {
+    Resident& R = s->res;
+    if (R.live.empty()) return;
+    if (R.stop_us < 0) R.stop_us = now;
+    if (now - R.stop_us < kResidentStopUs) return;
+    snprintf(s->err, sizeof(s->err), "resident mode: %d requests unfinished 5 s into shutdown",
+             (int)R.live.size());
+    for (Resident::Live& L : R.live)
+        if (!L.finished) finish_request(s, L.ticket, TDCT_EDEVICE, L.queued, now);
+    R.live.clear();
+    s->done.notify_all();
+}
+
+// Step 3 in resident mode: publishes admitted requests, oldest first, while
+// the queue and the tile ring have room, and makes sure a launch is on the
+// device while requests are live. Lock held.
+void resident_publish(tdct_server* s, double now) {
+    Resident& R = s->res;
+    bool published = false;
+    while (!s->admitted.empty()) {
+        const uint64_t t = s->admitted.front();
+        Req& q = s->reqs[t];
+        const uint64_t nt = (uint64_t)request_tiles(q.r);
+        // Slots and tile entries are reused only once every request
+        // published before the oldest live one has finished.
+        const uint64_t seq0 = R.live.empty() ? R.next_seq : R.live.front().seq;
+        const uint64_t tile0 = R.live.empty() ? R.next_tile : R.live.front().tile_base;
+        if (R.next_seq - seq0 >= R.ring_jobs || R.next_tile + nt - tile0 > R.ring_tiles) break;
+        s->admitted.pop_front();
+        const uint64_t seq = R.next_seq;
+        ResidentJob& J = R.ring[(uint32_t)seq & (R.ring_jobs - 1)];
+        const tdct_request& r = q.r;
+        char* out = s->arena_base + q.arena_off;
+        make_qconst(&r.Q, r.op == TDCT_OP_ENCODE ? r.keep : 64, &J.qc);
+        if (r.op == TDCT_OP_ENCODE)
+            fill_desc(OP_ENCODE, (const uint8_t*)r.input, r.in_stride, r.w, r.h, out, nullptr, 0, 0,
+                      true, &J.d);
+        else
+            fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(r.input), (uint8_t*)out, r.w,
+                      0, false, &J.d);
+        J.base = R.next_tile;
+        J.ntiles = (uint32_t)nt;
+        J.done_value = (uint32_t)(seq + 1);
+        R.live.push_back({t, seq, R.next_tile, (uint32_t)nt, (int32_t)R.live.size() + 1, false});
+        R.next_seq++;
+        R.next_tile += nt;
+        __atomic_store_n(R.ctrl, R.next_seq, __ATOMIC_RELEASE);
+        s->batch_reqs++;
+        published = true;
+    }
+    if (published) s->last_activity_us = now;
+    if (!R.live.empty() && !R.running) {
+        const int st = resident_launch(s);
+        if (st) {
+            memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
+            for (Resident::Live& L : R.live)
+                if (!L.finished) {
+                    finish_request(s, L.ticket, st, L.queued, now);
+                    L.finished = true;
+                }
+            while (!R.live.empty() && R.live.front().finished) R.live.pop_front();
+            s->done.notify_all();
+        }
+    }
+}
+
 void scheduler(tdct_server* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     std::vector<BatchItem> items;
@@ -385,6 +738,10 @@ void scheduler(tdct_server* s) {
             } else {
                 any_busy = true;
             }
+        }
+        if (s->cfg.resident) {
+            if (s->stop) resident_shutdown_watchdog(s, now);
+            any_busy |= resident_completions(s, now);
         }
         if (any_busy) {
             if (s->busy_since < 0) s->busy_since = now;
@@ -418,6 +775,7 @@ void scheduler(tdct_server* s) {
         s->st.arena_high_water = s->arena->high();
         // 3. launches
         double next_deadline = -1;
+        if (s->cfg.resident) resident_publish(s, now);
         for (Slot& sl : s->slots) {
             if (sl.busy || s->admitted.empty()) continue;
             const int maxb = s->cfg.batching ? std::max(1, s->cfg.max_batch) : 1;
@@ -468,7 +826,7 @@ void scheduler(tdct_server* s) {
         // While batches are in flight, or shortly after any activity, poll:
         // event completion and new arrivals are seen within microseconds.
         // Otherwise sleep until a submit, a release or the batching deadline.
-        bool busy_now = false;
+        bool busy_now = s->cfg.resident && !s->res.live.empty();
         for (Slot& sl : s->slots) busy_now |= sl.busy;
         const double tnow = s->now_us();
         if (busy_now || tnow - s->last_activity_us < kSpinUs) {
@@ -487,6 +845,7 @@ void scheduler(tdct_server* s) {
         }
     }
     if (s->busy_since >= 0) s->st.busy_us += s->now_us() - s->busy_since;
+    if (s->cfg.resident) __atomic_fetch_or(s->res.ctrl, kCtrlStop, __ATOMIC_RELEASE);
 }
 
 }  // namespace
@@ -509,7 +868,7 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
     s->fake = cfg->fake_device_us > 0;
     s->t0 = Clock::now();
     s->arena = new Arena(cfg->budget_bytes);
-    s->slots.resize((size_t)cfg->streams);
+    s->slots.resize(cfg->resident ? 0 : (size_t)cfg->streams);
     if (s->fake) {
         s->arena_base = (char*)malloc((size_t)cfg->budget_bytes);
         if (!s->arena_base) {
@@ -547,6 +906,17 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
             return e == hipErrorOutOfMemory ? TDCT_ENOMEM : TDCT_EDEVICE;
         }
     }
+    if (s->cfg.resident) {
+        const int st = resident_init(s);
+        if (st) {
+            resident_free(s);
+            if (s->fake) free(s->arena_base);
+            else hipFree(s->arena_base);
+            delete s->arena;
+            delete s;
+            return st;
+        }
+    }
     s->worker = std::thread(scheduler, s);
     *out = s;
     return TDCT_OK;
@@ -555,7 +925,8 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
 static int submit_locked(tdct_server* s, const tdct_request* req, bool release_on_done,
                          uint64_t* ticket) {
     const int64_t ob = output_bytes(*req);
-    if (Arena::round(reserve_bytes(*req)) > s->arena->size()) {
+    if (Arena::round(reserve_bytes(*req)) > s->arena->size() ||
+        (s->cfg.resident && request_tiles(*req) > (int64_t)s->res.ring_tiles)) {
         s->st.rejected++;
         return TDCT_ENOMEM;
     }
@@ -575,7 +946,7 @@ static int submit_locked(tdct_server* s, const tdct_request* req, bool release_o
 
 int tdct_server_submit(tdct_server* s, const tdct_request* req, uint64_t* ticket) {
     if (!s || !req || !ticket) return TDCT_EINVAL;
-    int st = validate_request(*req);
+    int st = validate_for(s, *req);
     if (st) return st;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -680,6 +1051,7 @@ void tdct_server_destroy(tdct_server* s) {
     }
     s->wake.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    if (s->cfg.resident) resident_free(s);
     if (s->fake) {
         free(s->arena_base);
     } else {
@@ -702,7 +1074,7 @@ int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* a
     if (!s || n < 0 || (n > 0 && (!reqs || !arrival_us))) return TDCT_EINVAL;
     int64_t kept = 0;
     for (int32_t k = 0; k < n; ++k) {
-        int st = validate_request(reqs[k]);
+        int st = validate_for(s, reqs[k]);
         if (st) return st;
         if (!reqs[k].host_io) kept += Arena::round(reserve_bytes(reqs[k]));
     }

@@ -1,0 +1,399 @@
+// Per-wave tile code of the codec for gfx950, shared by the batch kernels and
+// the resident serving kernel: coefficient staging through LDS, pixel loads
+// and stores, the encoder tile (two blocks per lane as packed int16 pairs)
+// and the decoder tile (one block per lane in int32).
+//
+// Thread mapping. Every lane owns whole 8x8 blocks, so both 1-D passes of
+// the separable transform (Section 3) run in registers without cross-lane
+// traffic:
+//  * encoder-side ops: a lane owns blocks first + l and first + 64 + l of its
+//    wave-tile and keeps pixel (r, c) of both as one packed int16 pair, so
+//    every v_pk_add/v_pk_sub does the butterfly of Section 2 for both blocks
+//    (the whole 2-D forward transform costs 1.75 VALU ops per pixel).
+//    Unshifted pixels keep every intermediate within 16 bits (|sum| <= 64 *
+//    255), and the level shift -128 moves only the DC term (rows 1..7 of T
+//    sum to zero), by -8192;
+//  * the decoder: a lane owns one block in int32, because with Q <= 4095 an
+//    arbitrary int16 input needs 32-bit intermediates.
+// A wave-tile is up to 128 (encoder) or 64 (decoder) consecutive blocks of
+// one image; rows of 64 consecutive blocks are contiguous, so pixel-side
+// accesses of a wave cover whole 512-byte runs of a row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tdct_device.hpp"
+
+namespace tdct {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+
+// Streaming accesses: every byte is touched once, so loads and stores carry
+// the non-temporal hint and do not displace other data in L2 / MALL.
+__device__ __forceinline__ v4u ld_nt4(const void* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+}
+__device__ __forceinline__ v2u ld_nt2(const void* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const v2u*>(p));
+}
+__device__ __forceinline__ void st_nt4(void* p, v4u v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(p));
+}
+__device__ __forceinline__ void st_nt2(void* p, v2u v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<v2u*>(p));
+}
+
+// LDS writes of this wave complete before its following LDS reads (and the
+// compiler keeps LDS accesses on their side of this point).
+__device__ __forceinline__ void lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Pack two int32 values (known to fit 16 bits) into one dword, low first.
+__device__ __forceinline__ uint32_t pack16(int lo, int hi) {
+    return __builtin_amdgcn_perm((uint32_t)hi, (uint32_t)lo, 0x05040100u);
+}
+
+// Pack four values in [0, 255] into one dword, first in the low byte.
+__device__ __forceinline__ uint32_t pack8(int b0, int b1, int b2, int b3) {
+    uint32_t lo = __builtin_amdgcn_perm((uint32_t)b1, (uint32_t)b0, 0x0c0c0400u);
+    uint32_t hi = __builtin_amdgcn_perm((uint32_t)b3, (uint32_t)b2, 0x04000c0cu);
+    return lo | hi;
+}
+
+// ---- coefficient-side staging through LDS ------------------------------------
+//
+// Every lane owns whole blocks, so the coefficients of one of its blocks form
+// CPL consecutive 16-byte chunks (CPL = 8: an int16 block; CPL = 4: an int8
+// block) of the contiguous run that 64 consecutive blocks occupy. Direct
+// stores would make every instruction touch 64 chunks CPL * 16 bytes apart.
+// Instead the wave writes its chunks to its own LDS slice and reads them back
+// so that instruction k moves chunks 64k .. 64k + 63, i.e. 1 KB of
+// consecutive bytes (and the reverse for the decoder's loads). Chunk m of
+// lane L sits at slot CPL * L + (m ^ swz(L)); the XOR puts any 8 and any 16
+// consecutive lanes of both access patterns on distinct 16-byte bank groups,
+// whether the LDS has 32 or 64 four-byte banks.
+template <int CPL>
+__device__ __forceinline__ uint32_t swz(uint32_t L) {
+    return CPL == 8 ? ((L ^ (L >> 3)) & 7u) : (((L >> 1) ^ (L >> 2)) & 3u);
+}
+
+// Stores the run of 64 * CPL chunks at dst (only its first nchunks) from
+// lane-owned chunks.
+template <int CPL>
+__device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint32_t nchunks,
+                                          v4u* dst, uint32_t lane) {
+#pragma unroll
+    for (int m = 0; m < CPL; ++m) wl[CPL * lane + ((uint32_t)m ^ swz<CPL>(lane))] = mine[m];
+    lds_fence();
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const uint32_t c = 64u * k + lane;
+        const uint32_t L = c / CPL, m = c % CPL;
+        const v4u v = wl[CPL * L + (m ^ swz<CPL>(L))];
+        if (c < nchunks) st_nt4(dst + c, v);
+    }
+    asm volatile("" ::: "memory");
+}
+
+// Loads the run of 512 chunks at src (only its first nchunks; the rest read
+// as zero) and hands every lane the 8 chunks of its own int16 block.
+__device__ __forceinline__ void stage_in(v4u* wl, const v4u* src, uint32_t nchunks, uint32_t lane,
+                                         v4u (&mine)[8]) {
+    v4u tmp[8];
+    if (nchunks == 512) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tmp[k] = ld_nt4(src + 64u * k + lane);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t c = 64u * k + lane;
+            tmp[k] = c < nchunks ? ld_nt4(src + c) : (v4u){0u, 0u, 0u, 0u};
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t c = 64u * k + lane;
+        const uint32_t L = c >> 3, m = c & 7u;
+        wl[8 * L + (m ^ swz<8>(L))] = tmp[k];
+    }
+    lds_fence();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) mine[m] = wl[8 * lane + ((uint32_t)m ^ swz<8>(lane))];
+    asm volatile("" ::: "memory");
+}
+
+// ---- pixel side ---------------------------------------------------------------
+
+__device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int flags,
+                                           uint32_t (&R)[8][2]) {
+    if (flags & F_SRC8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const v2u v = ld_nt2(p + r * stride);
+            R[r][0] = v.x;
+            R[r][1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint8_t* q = p + r * stride;
+            R[r][0] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) |
+                      ((uint32_t)q[3] << 24);
+            R[r][1] = (uint32_t)q[4] | ((uint32_t)q[5] << 8) | ((uint32_t)q[6] << 16) |
+                      ((uint32_t)q[7] << 24);
+        }
+    }
+}
+
+__device__ __forceinline__ void store_rows8(uint8_t* p, int64_t stride, int flags,
+                                            const uint32_t (&R)[8][2]) {
+    if (flags & F_DST8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) st_nt2(p + r * stride, (v2u){R[r][0], R[r][1]});
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            uint8_t* q = p + r * stride;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                q[c] = (uint8_t)(R[r][0] >> (8 * c));
+                q[4 + c] = (uint8_t)(R[r][1] >> (8 * c));
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t block_offset(int64_t stride, uint32_t nbx, uint32_t b) {
+    const uint32_t by = b / nbx;
+    const uint32_t bx = b - by * nbx;
+    return (int64_t)(8 * by) * stride + 8 * bx;
+}
+
+// ---- decoder core ----------------------------------------------------------
+
+// Inverse transform of one block of dequantised coefficients W'_ij (natural
+// order) into 8 rows of 8 pixels: floor((S + 32) / 64) + 128, clamped.
+__device__ __forceinline__ void reconstruct(int (&W)[64], uint32_t (&px)[8][2]) {
+    // +32 rounds floor((S + 32) / 64); +8192 = 64 * 128 undoes the level
+    // shift. Column 0 of T^t is all ones, so adding both to W'_00 adds them
+    // to every S_rc.
+    W[0] += 32 + 8192;
+    inv8x8(W);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        int p[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) p[c] = min(max(W[8 * r + c] >> 6, 0), 255);
+        px[r][0] = pack8(p[0], p[1], p[2], p[3]);
+        px[r][1] = pack8(p[4], p[5], p[6], p[7]);
+    }
+}
+
+// Dequantise + inverse transform of one block whose int16 coefficients sit in
+// 32 dwords (natural order, two per dword), producing 8 rows of 8 pixels.
+template <class QC>
+__device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC& qc,
+                                             uint32_t (&px)[8][2]) {
+    int W[64];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        // |q| <= 2^15 and Q <= 4095 fit the 24-bit multiplier exactly.
+        W[2 * k] = __mul24((int)(short)(qp[k] & 0xffffu), qc.Q[2 * k]);
+        W[2 * k + 1] = __mul24((int)qp[k] >> 16, qc.Q[2 * k + 1]);
+    }
+    reconstruct(W, px);
+}
+
+// ---- encoder tile ------------------------------------------------------------
+//
+// Lane l owns blocks first + l (a) and first + 64 + l (b) of the tile. The
+// rows of 64 consecutive blocks are contiguous, so each pixel load covers a
+// 512-byte run, and the coefficients of all a-blocks (then all b-blocks) are
+// one contiguous 8 KB run for the staged stores.
+
+template <int OP, class QC>
+__device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, uint32_t lane, v4u* wl) {
+    const bool va = lane < count, vb = lane + 64u < count;
+    const uint32_t nbx = (uint32_t)d.nbx;
+    const uint32_t ba = first + lane, bb = ba + 64u;
+
+    uint32_t A[8][2], B[8][2];
+    if (count == (uint32_t)kEncTileBlocks && (d.flags & F_SRC8)) {
+        const uint8_t* pa = d.src + block_offset(d.src_stride, nbx, ba);
+        const uint8_t* pb = d.src + block_offset(d.src_stride, nbx, bb);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const v2u x = ld_nt2(pa + r * d.src_stride), y = ld_nt2(pb + r * d.src_stride);
+            A[r][0] = x.x;
+            A[r][1] = x.y;
+            B[r][0] = y.x;
+            B[r][1] = y.y;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) A[r][0] = A[r][1] = B[r][0] = B[r][1] = 0x80808080u;
+        if (va) load_rows8(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, A);
+        if (vb) load_rows8(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, B);
+    }
+
+    // Pixel (r, c) of both blocks as a packed (a, b) int16 pair.
+    s16x2 v[64];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t k = (uint32_t)(c & 3);
+            const uint32_t sel = k | (0x0cu << 8) | ((4u + k) << 16) | (0x0cu << 24);
+            v[8 * r + c] = as_s16x2(__builtin_amdgcn_perm(B[r][c >> 2], A[r][c >> 2], sel));
+        }
+    }
+    fwd8x8(v);
+    v[0] -= (s16x2){8192, 8192};
+
+    const uint32_t na = min(count, 64u), nb = count > 64u ? count - 64u : 0u;
+    if constexpr (OP == OP_FORWARD) {
+        if (va) {
+            int32_t* oa = reinterpret_cast<int32_t*>(d.coef) + (int64_t)ba * 64;
+#pragma unroll
+            for (int k = 0; k < 64; k += 4)
+                st_nt4(oa + k, (v4u){(uint32_t)(int)v[k].x, (uint32_t)(int)v[k + 1].x,
+                                     (uint32_t)(int)v[k + 2].x, (uint32_t)(int)v[k + 3].x});
+        }
+        if (vb) {
+            int32_t* ob = reinterpret_cast<int32_t*>(d.coef) + (int64_t)bb * 64;
+#pragma unroll
+            for (int k = 0; k < 64; k += 4)
+                st_nt4(ob + k, (v4u){(uint32_t)(int)v[k].y, (uint32_t)(int)v[k + 1].y,
+                                     (uint32_t)(int)v[k + 2].y, (uint32_t)(int)v[k + 3].y});
+        }
+    } else if constexpr (OP == OP_ENCODE_I8ZZ) {
+        // int8, zigzag order: 64 bytes (4 chunks) per block.
+        v4u ma[4], mb[4];
+#pragma unroll
+        for (int n = 0; n < 64; n += 16) {
+            uint32_t wa[4], wb[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                int a4[4], b4[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = kZigzag.order[n + 4 * g + t];
+                    // t's bits grow with q, so saturating them saturates q;
+                    // the low byte is then q's two's-complement byte.
+                    a4[t] = (int)(min(max(quant_bits(v[k].x, qc.r[k]), kRoundMagicBits - 128u),
+                                      kRoundMagicBits + 127u) & 0xffu);
+                    b4[t] = (int)(min(max(quant_bits(v[k].y, qc.r[k]), kRoundMagicBits - 128u),
+                                      kRoundMagicBits + 127u) & 0xffu);
+                }
+                wa[g] = pack8(a4[0], a4[1], a4[2], a4[3]);
+                wb[g] = pack8(b4[0], b4[1], b4[2], b4[3]);
+            }
+            ma[n / 16] = (v4u){wa[0], wa[1], wa[2], wa[3]};
+            mb[n / 16] = (v4u){wb[0], wb[1], wb[2], wb[3]};
+        }
+        v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 4;
+        stage_out<4>(wl, ma, 4 * na, out, lane);
+        stage_out<4>(wl, mb, 4 * nb, out + 256, lane);
+    } else if constexpr (OP == OP_ROUNDTRIP_NC) {
+        // Encode and decode without storing coefficients. The rounding
+        // float's low 24 bits are 0x400000 + q (|q| < 2^22), so one 24-bit
+        // multiply-add gives W' = q Q directly: (0x400000 + q) Q - (Q << 22),
+        // exact modulo 2^32 and |q Q| < 2^31.
+        uint32_t px[8][2];
+        if (va) {
+            int W[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k)
+                W[k] = (int)(__umul24(quant_bits(v[k].x, qc.r[k]), (uint32_t)qc.Q[k]) -
+                             ((uint32_t)qc.Q[k] << 22));
+            reconstruct(W, px);
+            store_rows8(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+        }
+        if (vb) {
+            int W[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k)
+                W[k] = (int)(__umul24(quant_bits(v[k].y, qc.r[k]), (uint32_t)qc.Q[k]) -
+                             ((uint32_t)qc.Q[k] << 22));
+            reconstruct(W, px);
+            store_rows8(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
+        }
+    } else {
+        // OP_ENCODE / OP_ROUNDTRIP: int16 coefficients, natural order.
+        uint32_t qa[32], qb[32];
+#pragma unroll
+        for (int k = 0; k < 64; k += 2) {
+            qa[k / 2] = pack16((int)quant_bits(v[k].x, qc.r[k]), (int)quant_bits(v[k + 1].x, qc.r[k + 1]));
+            qb[k / 2] = pack16((int)quant_bits(v[k].y, qc.r[k]), (int)quant_bits(v[k + 1].y, qc.r[k + 1]));
+        }
+        const bool write_coef = (OP == OP_ENCODE) || (d.flags & F_COEF);
+        if (write_coef) {
+            v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 8;
+            v4u m8[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) m8[m] = (v4u){qa[4 * m], qa[4 * m + 1], qa[4 * m + 2], qa[4 * m + 3]};
+            stage_out<8>(wl, m8, 8 * na, out, lane);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) m8[m] = (v4u){qb[4 * m], qb[4 * m + 1], qb[4 * m + 2], qb[4 * m + 3]};
+            stage_out<8>(wl, m8, 8 * nb, out + 512, lane);
+        }
+        if constexpr (OP == OP_ROUNDTRIP) {
+            uint32_t px[8][2];
+            if (va) {
+                decode_block(qa, qc, px);
+                store_rows8(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+            }
+            if (vb) {
+                decode_block(qb, qc, px);
+                store_rows8(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
+            }
+        }
+    }
+}
+
+// ---- decoder tile -----------------------------------------------------------
+//
+// Lane l owns block first + l.
+
+template <class QC>
+__device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, uint32_t lane, v4u* wl) {
+    v4u mine[8];
+    stage_in(wl, reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, mine);
+    if (lane >= count) return;
+    uint32_t qp[32];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        qp[4 * m] = mine[m].x;
+        qp[4 * m + 1] = mine[m].y;
+        qp[4 * m + 2] = mine[m].z;
+        qp[4 * m + 3] = mine[m].w;
+    }
+    uint32_t px[8][2];
+    decode_block(qp, qc, px);
+    const uint32_t b = first + lane;
+    store_rows8(d.dst + block_offset(d.dst_stride, (uint32_t)d.nbx, b), d.dst_stride, d.flags, px);
+}
+
+template <int OP, class QC>
+__device__ __forceinline__ void run_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, uint32_t lane, v4u* wl) {
+    if constexpr (OP == OP_DECODE)
+        dec_tile(d, qc, first, count, lane, wl);
+    else
+        enc_tile<OP>(d, qc, first, count, lane, wl);
+}
+
+// LDS bytes one wave needs for a set of ops (bit i = op i).
+__host__ __device__ constexpr uint32_t lds_wave_bytes(int ops) {
+    return (ops & ((1 << OP_ENCODE) | (1 << OP_ROUNDTRIP) | (1 << OP_DECODE))) ? 8192u
+           : (ops & (1 << OP_ENCODE_I8ZZ)) ? 4096u
+                                           : 0u;
+}
+
+}  // namespace tdct

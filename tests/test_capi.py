@@ -228,3 +228,81 @@ def test_host_io_request_needs_a_host_output(tdct):
         assert tdct.tdct_server_wait(s, t).output == 0x2000
     finally:
         tdct.tdct_server_destroy(s)
+
+
+# ---- resident mode on the fake device ----------------------------------------
+# A host thread plays the resident kernel's part of the queue protocol. It
+# checks, before raising each done flag, that the request's queue slot and
+# tile-ring entries were not reused early, and reports a violation through
+# tdct_server_last_error.
+
+def _resident(tdct, budget=1 << 26, **kw):
+    kw.setdefault("fake_device_us", 100)
+    return tdct.tdct_server_create(tdct.server_cfg(budget, resident=1, **kw))
+
+
+def test_fake_resident_wraps_both_rings_without_reuse(tdct):
+    # 4 queue slots and 16 tile slots; requests of 1 to 16 tiles (a tile is 128
+    # blocks encoding, 64 decoding: 256 x 256 is 8 tiles encoded, 16 decoded)
+    s = _resident(tdct, resident_jobs=4, resident_tiles=16, fake_device_us=60)
+    try:
+        sizes = [(64, 32), (256, 256), (128, 64), (256, 128), (32, 32), (256, 256), (64, 64)]
+        tickets = []
+        for k in range(60):
+            w, h = sizes[k % len(sizes)]
+            tickets.append(tdct.tdct_server_submit(s, _req(tdct, k % 2, w, h)))
+        deadline = time.time() + 10  # a protocol fault shows as a request that never ends
+        while tdct.tdct_server_stats(s)["completed"] < 60 and time.time() < deadline:
+            time.sleep(0.002)
+        assert tdct.tdct_server_last_error(s) == ""
+        for t in tickets:
+            r = tdct.tdct_server_poll(s, t)
+            assert r.status == tdct.TDCT_OK and 1 <= r.batch_size <= 4
+        st = tdct.tdct_server_stats(s)
+        assert st["completed"] == 60 and st["failed"] == 0 and st["batches"] >= 1
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_resident_relaunches_after_idle_exit(tdct):
+    s = _resident(tdct, resident_idle_us=1000, fake_device_us=50)
+    try:
+        t1 = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 64, 64))
+        assert tdct.tdct_server_wait(s, t1).status == tdct.TDCT_OK
+        time.sleep(0.02)  # well past the idle limit: the stand-in kernel has exited
+        t2 = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_DECODE, 64, 64))
+        assert tdct.tdct_server_wait(s, t2).status == tdct.TDCT_OK
+        assert tdct.tdct_server_stats(s)["batches"] == 2  # two launches
+        assert tdct.tdct_server_last_error(s) == ""
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_resident_refuses_what_it_cannot_serve(tdct):
+    s = _resident(tdct, resident_tiles=8)
+    try:
+        t = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 256, 256))  # 8 tiles: fits
+        assert tdct.tdct_server_wait(s, t).status == tdct.TDCT_OK
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_submit(s, _req(tdct, tdct.OP_DECODE, 256, 256))  # 16 tiles
+        assert e.value.status == tdct.TDCT_ENOMEM
+        assert tdct.tdct_server_stats(s)["rejected"] == 1
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_submit(s, tdct.request(tdct.OP_DECODE, 8, 8, 0x1008, np.ones(64),
+                                                    host_output=0x2000))
+        assert e.value.status == tdct.TDCT_EINVAL
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_resident_replay_and_shutdown_with_work_in_flight(tdct):
+    s = _resident(tdct, resident_jobs=8, fake_device_us=300)
+    try:
+        reqs = [_req(tdct, k % 2, 32, 64) for k in range(40)]
+        tk, lat, st = tdct.tdct_server_replay(s, reqs, [k * 100.0 for k in range(40)])
+        assert all(x == tdct.TDCT_OK for x in st) and min(lat) >= 300
+        assert tdct.tdct_server_stats(s)["arena_bytes_in_use"] == 0
+        for _ in range(10):
+            tdct.tdct_server_submit(s, _req(tdct, 0, 64, 64))
+    finally:
+        tdct.tdct_server_destroy(s)  # the ten in flight finish first

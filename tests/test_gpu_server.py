@@ -179,3 +179,59 @@ def test_host_payloads_equal_device_resident_results(tdct):
         assert np.array_equal(outs[k].numpy(), dev[k]), k
     for k in range(0, n, 7):
         assert np.array_equal(outs[k].numpy(), W.expected(k)), k
+
+
+# ---- resident mode -----------------------------------------------------------
+# Small queue and tile ring, so that both wrap many times during the mix.
+RESIDENT = dict(resident=1, resident_jobs=16, resident_tiles=1024, resident_idle_us=5000)
+
+
+def test_resident_mix_equals_stream_mode_and_oracle(tdct):
+    W = Workload(tdct, rate=10000.0, seconds=0.03, seed=58)
+    n = len(W.reqs)
+    assert n > 100
+    budget = 1 << 30
+    res, lat, st = _serve(tdct, W, tdct.server_cfg(budget, **RESIDENT))
+    assert st["completed"] == n and st["failed"] == 0
+    assert st["batches"] >= 1 and st["arena_high_water"] <= budget
+    per, _, _ = _serve(tdct, W, tdct.server_cfg(budget, streams=4, max_batch=1, batching=0))
+    for k in range(n):
+        assert np.array_equal(res[k], per[k]), k
+    rng = np.random.default_rng(2)
+    for k in sorted(set(rng.choice(n, 30, replace=False).tolist())):
+        assert np.array_equal(res[k], W.expected(k)), k
+
+
+def test_resident_single_worker_and_wrap(tdct):
+    """One worker wave claims every tile; 4 queue slots and 256 tile slots."""
+    W = Workload(tdct, rate=20000.0, seconds=0.005, seed=59)
+    cfg = tdct.server_cfg(1 << 30, resident=1, resident_workers=1, resident_jobs=4,
+                          resident_tiles=256, resident_idle_us=5000)
+    res, _, st = _serve(tdct, W, cfg, arrival=False)
+    assert st["completed"] == len(W.reqs) and st["failed"] == 0
+    for k in range(len(W.reqs)):
+        assert np.array_equal(res[k], W.expected(k)), k
+
+
+def test_resident_kernel_relaunches_after_idle_exit(tdct):
+    import time
+    import torch
+    hip = _hip()
+    img = synth.textured(256, 128, 9)
+    dimg = torch.from_numpy(img).cuda()
+    Q = synth.qtable(1, 3)
+    srv = tdct.tdct_server_create(tdct.server_cfg(1 << 24, resident=1, resident_idle_us=2000,
+                                                  resident_workers=4))
+    try:
+        for _ in range(2):
+            t = tdct.tdct_server_submit(srv, tdct.request(tdct.OP_ENCODE, 256, 128, dimg, Q, keep=20))
+            r = tdct.tdct_server_wait(srv, t)
+            assert r.status == tdct.TDCT_OK
+            got = _read(hip, r.output, r.output_bytes)
+            assert np.array_equal(got, O.quantise(img, Q, 20).view(np.uint8).reshape(-1))
+            tdct.tdct_server_release(srv, t)
+            time.sleep(0.05)  # past the idle limit: the kernel exits
+        assert tdct.tdct_server_stats(srv)["batches"] == 2
+        assert tdct.tdct_server_last_error(srv) == ""
+    finally:
+        tdct.tdct_server_destroy(srv)
