@@ -14,11 +14,21 @@ The JSON line also carries:
                 over its average launch time, measured with HIP events on the
                 launch stream, against the 8 TB/s HBM peak;
   cpu_baseline  the CPU oracle (dense 8x8 integer products) encoding and
-                decoding a bounded sample of the same images on the host cores;
+                decoding a bounded sample of the same images on the host cores
+                (and on one core);
+and, unless --no-extras:
+  fused_roundtrip  encode + decode fused with no coefficients in HBM;
+  per_image     the same 64-image batch with one plain launch per image;
+  latency_512   one 512 x 512 image: per-call latency of each plain entry
+                point, and the PSNR of a zonal keep-10 reconstruction;
+  ceiling       stream probes: the part's practical copy/read/write rates;
+  video         256 4:2:0 frames to int8 zigzag, one graph vs one launch per plane;
   batched       10,000 ragged images as one persistent launch replayed from a
-                hipGraph vs one plain launch per image (--no-extras skips);
-  serving       Poisson request streams served with continuous batching vs a
-                plain launch per request: p50/p99 latency and Gpixel/s.
+                hipGraph vs one plain launch per image;
+  serving       Poisson request streams served with continuous batching, with a
+                plain launch per request, by the resident kernel, and with host
+                payloads over PCIe: p50/p99 latency and Gpixel/s;
+  quality       (--quality) the zonal-coding sweep against the exact DCT.
 """
 from __future__ import annotations
 
@@ -123,6 +133,15 @@ def cpu_baseline(W, min_s=10.0, max_passes=16):
         if time.perf_counter() - t0 >= min_s:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one core, over a smaller sample
+    px1, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < min_s / 4:
+        img = synth.batch_view(W["buf"], W["off"], W["strides"], W["sizes"], 0)
+        w, h = W["sizes"][0]
+        q = O.quantise(img, W["qs"][0], 64, threads=1)
+        O.inverse(q, W["qs"][0], w, h, threads=1)
+        px1 += w * h
+    dt1 = time.perf_counter() - t1
     cpu_model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -133,7 +152,82 @@ def cpu_baseline(W, min_s=10.0, max_passes=16):
         pass
     return {"value": round(px / dt / 1e9, 4), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
             "sample": "encode+decode of %d images of 4096x4096 from the 64-image batch (%.1f s wall), "
-                      "dense 8x8 integer products, %d threads, %s" % (done, dt, threads, cpu_model)}
+                      "dense 8x8 integer products, %d threads, %s" % (done, dt, threads, cpu_model),
+            "single_core": {"value": round(px1 / dt1 / 1e9, 4), "unit": "Gpixel/s",
+                            "sample": "encode+decode of image 0, %d passes in %.1f s, 1 thread"
+                                      % (px1 // (W["sizes"][0][0] * W["sizes"][0][1]), dt1)}}
+
+
+def per_image_leg(tdct, torch, W, stream, reps=5):
+    """The 64-image batch coded with one plain launch per image (all encodes,
+    then all decodes): the comparison for the one-launch batch form."""
+    tdct.tdct_run_per_image(W["enc"], W["qs"], stream)
+    tdct.tdct_run_per_image(W["dec"], W["qs"], stream)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        tdct.tdct_run_per_image(W["enc"], W["qs"], stream)
+        tdct.tdct_run_per_image(W["dec"], W["qs"], stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    med = sorted(ms)[len(ms) // 2]
+    return {"launches": 2 * len(W["enc"]), "ms": round(med, 4),
+            "gpx_s": round(W["pixels"] / (med / 1e3) / 1e9, 2)}
+
+
+def latency_leg(tdct, torch, stream, side=512, reps=100):
+    """One 512 x 512 image (seed 1), Q = 1: the int32 forward transform, the
+    quantiser with zonal keep 10, the decoder, and the fused round trip, each
+    as the median of `reps` event-timed calls; the input (256 KiB) is cache
+    resident, so these are latencies, not roofline figures. Also the host
+    clock from call to completion of one round trip, and the PSNR of the
+    keep-10 reconstruction."""
+    import numpy as np
+
+    import synth
+    img = synth.plane(side, side, 1)
+    one = np.ones(64, np.uint16)
+    src = torch.from_numpy(img).cuda()
+    nblk = (side // 8) ** 2
+    Y = torch.empty((nblk, 64), dtype=torch.int32, device="cuda")
+    q = torch.empty((nblk, 64), dtype=torch.int16, device="cuda")
+    rec = torch.empty_like(src)
+    rt = torch.empty_like(src)
+    sse = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ops = {
+        "forward_int32": lambda: tdct.tdct_forward(src, side, side, side, Y, stream),
+        "quantise_keep10": lambda: tdct.tdct_quantise(src, side, side, side, one, 10, q, stream),
+        "inverse": lambda: tdct.tdct_inverse(q, one, side, side, rec, side, stream),
+        "roundtrip_keep10": lambda: tdct.tdct_roundtrip(src, side, side, side, one, 10, None, rt, side,
+                                                        stream),
+    }
+    out = {"side": side, "reps": reps}
+    for name, f in ops.items():
+        f()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        for k in range(reps):
+            ev[2 * k].record(stream)
+            f()
+            ev[2 * k + 1].record(stream)
+        torch.cuda.synchronize()
+        t = sorted(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(reps))
+        out[name + "_us"] = round(1e3 * t[reps // 2], 2)
+    wall = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ops["roundtrip_keep10"]()
+        stream.synchronize()
+        wall.append(time.perf_counter() - t0)
+    out["roundtrip_keep10_call_to_done_us"] = round(1e6 * sorted(wall)[reps // 2], 2)
+    tdct.tdct_sse(src, side, rec, side, side, side, sse.data_ptr(), stream)
+    torch.cuda.synchronize()
+    mse = float(sse.item()) / (side * side)
+    out["psnr_keep10_db"] = round(10 * np.log10(255.0 ** 2 / mse), 3) if mse > 0 else None
+    return out
 
 
 def batched_leg(tdct, torch, stream, n=10000, reps=5):
@@ -567,9 +661,13 @@ def main():
     if not args.no_extras:
         log("fused round-trip leg...")
         result["fused_roundtrip"] = fused_leg(tdct, torch, W, stream)
+        log("per-image launches of the same batch...")
+        result["per_image"] = per_image_leg(tdct, torch, W, stream)
     del W
     torch.cuda.empty_cache()
     if not args.no_extras:
+        log("latency leg (512 x 512)...")
+        result["latency_512"] = latency_leg(tdct, torch, stream)
         log("ceiling leg...")
         result["ceiling"] = ceiling_leg(tdct, torch, stream)
         log("video leg...")
