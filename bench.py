@@ -299,18 +299,39 @@ def ceiling_leg(tdct, torch, stream, mib=1024, reps=5):
     return {"unit": "GB/s", "mib_per_unit_side": mib, **out}
 
 
-def fused_leg(tdct, torch, W, stream, reps=10):
+# VALU issue peak of the part: 256 CUs x 4 SIMDs x 16 lanes per clock at
+# 2.4 GHz = 39.3 T lane-operations/s (non-packed 32-bit; a wave64 VALU
+# instruction occupies one SIMD for 4 clocks).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def load_valu(name: str):
+    """VALU instructions per launch from a committed rocprofv3 counter
+    summary, or None when absent or taken from a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "valu_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source") != kernel_source_hash():
+        return None
+    return d
+
+
+def fused_leg(tdct, torch, W, stream, reps=10, tune=None):
     """Encode + decode in one pass with no coefficients in HBM (2 B/px) on the
-    same 64 x 4096^2 batch."""
+    same 64 x 4096^2 batch. Bound by VALU issue, not HBM: its roofline is the
+    counted VALU instructions per launch over the launch time, against the
+    part's VALU issue peak."""
     n = len(W["sizes"])
     side = W["sizes"][0][0]
     base = W["src"].data_ptr()
     descs = [tdct.image_desc(tdct.OP_ROUNDTRIP, side, side, qtab=i, keep=64, src=base + int(W["off"][i]),
                              src_stride=side, coef=None, dst=W["dst"][i], dst_stride=side)
              for i in range(n)]
-    plan = tdct.tdct_batch_plan(descs, W["qs"])
+    plan = tdct.tdct_batch_plan(descs, W["qs"], tune=tune)
     try:
-        tune = tdct.tdct_autotune(plan, stream, reps=2)
+        if tune is None:
+            tune = tdct.tdct_autotune(plan, stream, reps=2)
         tdct.tdct_batch_run(plan, stream)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
         for k in range(reps):
@@ -322,9 +343,17 @@ def fused_leg(tdct, torch, W, stream, reps=10):
     finally:
         tdct.tdct_plan_free(plan)
     px = W["pixels"]
-    return {"kernel": "batch_kernel<4> (round trip, coefficients kept in registers)", "tune": tune,
+    valu = load_valu("roundtrip_64x4096")
+    roof = None
+    if valu:
+        lane_ops = valu["valu_insts_per_launch"] * 64
+        achieved = lane_ops / (ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "T VALU lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "valu_lane_ops_per_px": round(lane_ops / px, 3)}
+    return {"kernel": "batch_kernel<32> (round trip, coefficients kept in registers)", "tune": tune,
             "ms": round(ms, 4), "gpx_s": round(px / (ms / 1e3) / 1e9, 1),
-            "gbs": round(2 * px / (ms / 1e3) / 1e9, 1), "bytes_per_px": 2}
+            "gbs": round(2 * px / (ms / 1e3) / 1e9, 1), "bytes_per_px": 2, "roofline": roof}
 
 
 def video_leg(tdct, torch, stream, frames=256, reps=5):
@@ -569,6 +598,10 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--quality", action="store_true",
                     help="also run the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated subset of the extra legs to run (default: all)")
+    ap.add_argument("--fused-tune", default="",
+                    help="fixed launch shape 'WPG,GPC,TW' for the fused round trip")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -658,24 +691,38 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)...")
         result["cpu_baseline"] = cpu_baseline(W)
-    if not args.no_extras:
+    legs = set(args.legs.split(",")) if args.legs else None
+
+    def want(name):
+        return not args.no_extras and (legs is None or name in legs)
+
+    if want("fused_roundtrip"):
         log("fused round-trip leg...")
-        result["fused_roundtrip"] = fused_leg(tdct, torch, W, stream)
+        ft = None
+        if args.fused_tune:
+            a, b, c = (int(x) for x in args.fused_tune.split(","))
+            ft = dict(waves_per_group=a, groups_per_cu=b, tile_waves=c)
+        result["fused_roundtrip"] = fused_leg(tdct, torch, W, stream, tune=ft)
+    if want("per_image"):
         log("per-image launches of the same batch...")
         result["per_image"] = per_image_leg(tdct, torch, W, stream)
     del W
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if want("latency_512"):
         log("latency leg (512 x 512)...")
         result["latency_512"] = latency_leg(tdct, torch, stream)
+    if want("ceiling"):
         log("ceiling leg...")
         result["ceiling"] = ceiling_leg(tdct, torch, stream)
+    if want("video"):
         log("video leg...")
         result["video"] = video_leg(tdct, torch, stream)
         torch.cuda.empty_cache()
+    if want("batched"):
         log("batched leg...")
         result["batched"] = batched_leg(tdct, torch, stream)
         torch.cuda.empty_cache()
+    if want("serving"):
         log("serving leg...")
         result["serving"] = serving_leg(tdct, torch, args.serving_seconds)
     if args.quality:
