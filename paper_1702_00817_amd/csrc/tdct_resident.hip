@@ -156,6 +156,12 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
         }
         pend_items = 0;
     };
+    // The job held in LDS covers items [cur_base, cur_end); item indices are
+    // unique, so a ticket in that range is another item of the same job.
+    uint64_t cur_base = 0, cur_end = 0;
+    ImgDesc d{};
+    uint32_t ntiles = 0, per = 1, tb = kEncTileBlocks, done_value = 0, slot = 0;
+    const ResidentJob* J = reinterpret_cast<const ResidentJob*>(jl);
     while (true) {
         // A ticket is the index of the next work item this wave codes; taking
         // one always succeeds, and the wave then waits for that item to be
@@ -179,25 +185,30 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
             }
             if (state == 2) break;
         }
-        // item t's entry, its job copy and count were released before the
-        // publication that covered t
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const uint32_t slot = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                                  &a.item_slot[(uint32_t)t & imask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
-                              (a.ring_jobs - 1);
-        if (slot != pend_slot) count_off();
-        jl[k] = reinterpret_cast<const v4u*>(a.jobs + slot)[k];
-        lds_fence();
-        const ResidentJob* J = reinterpret_cast<const ResidentJob*>(jl);
-        ImgDesc d = uniform_copy(&J->d);
-        d.src = global_ptr(d.src);
-        d.dst = global_ptr(d.dst);
-        d.coef = global_ptr(d.coef);
-        const uint64_t base = first_lane64(J->base);
-        const uint32_t ntiles = __builtin_amdgcn_readfirstlane(J->ntiles);
-        const uint32_t per = item_tiles(ntiles, a.workers);
-        const uint32_t tb = (uint32_t)tile_blocks(d.op);
-        const uint64_t tile0 = (t - base) * per;
+        if (t < cur_base || t >= cur_end) {
+            // A new job: item t's entry, the job copy and count were released
+            // before the publication that covered t, and the job's inputs
+            // were written before it was queued; the acquire also drops any
+            // older copy of them from this wave's caches.
+            count_off();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            slot = __builtin_amdgcn_readfirstlane(__hip_atomic_load(&a.item_slot[(uint32_t)t & imask],
+                                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+                   (a.ring_jobs - 1);
+            jl[k] = reinterpret_cast<const v4u*>(a.jobs + slot)[k];
+            lds_fence();
+            d = uniform_copy(&J->d);
+            d.src = global_ptr(d.src);
+            d.dst = global_ptr(d.dst);
+            d.coef = global_ptr(d.coef);
+            cur_base = first_lane64(J->base);
+            ntiles = __builtin_amdgcn_readfirstlane(J->ntiles);
+            done_value = __builtin_amdgcn_readfirstlane(J->done_value);
+            per = item_tiles(ntiles, a.workers);
+            cur_end = cur_base + (ntiles + per - 1) / per;
+            tb = (uint32_t)tile_blocks(d.op);
+        }
+        const uint64_t tile0 = (t - cur_base) * per;
         const uint64_t tile1 = min(tile0 + per, (uint64_t)ntiles);
         for (uint64_t tile = tile0; tile < tile1; ++tile) {
             const uint64_t first = tile * tb;
@@ -209,7 +220,7 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
                 run_tile<OP_DECODE>(d, J->qc, (uint32_t)first, count, lane, wl);
         }
         pend_slot = slot;
-        pend_done = __builtin_amdgcn_readfirstlane(J->done_value);
+        pend_done = done_value;
         if (++pend_items >= kMaxPendingItems) count_off();
     }
     count_off();
