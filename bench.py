@@ -277,15 +277,21 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
             "speedup": round(per_s / graph_s, 2), "bytes_per_px": 4}
 
 
-def ceiling_leg(tdct, torch, stream, mib=1024, reps=5):
+PROBES = (("copy", 32), ("read", 16), ("write", 16), ("read1_write2", 48), ("read2_write1", 48))
+
+
+def ceiling_leg(tdct, torch, stream, mib=1024, reps=5, names=None):
     """HBM ceilings on this part: the codec's access mixes without arithmetic."""
     units = (mib << 20) // 16
     a = torch.ones(2 * units * 16, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     out = {}
-    for kind, name, per_unit in ((tdct.PROBE_COPY, "copy", 32), (tdct.PROBE_READ, "read", 16),
-                                 (tdct.PROBE_WRITE, "write", 16), (tdct.PROBE_R1W2, "read1_write2", 48),
-                                 (tdct.PROBE_R2W1, "read2_write1", 48)):
+    kinds = {"copy": tdct.PROBE_COPY, "read": tdct.PROBE_READ, "write": tdct.PROBE_WRITE,
+             "read1_write2": tdct.PROBE_R1W2, "read2_write1": tdct.PROBE_R2W1}
+    for name, per_unit in PROBES:
+        if names and name not in names:
+            continue
+        kind = kinds[name]
         tdct.tdct_stream_probe(kind, a, b, units, stream)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
         for k in range(reps):
@@ -662,9 +668,15 @@ def main():
     bytes_launch = 3 * px
     achieved = bytes_launch / (dom_ms / 1e3) / 1e9
     traffic = load_traffic(dom_name + "_64x4096")
+    # the part's practical rate for the dominant kernel's access mix: the
+    # same bytes streamed with no arithmetic (1 read : 2 writes for the
+    # encoder, 2 : 1 for the decoder)
+    mix = "read1_write2" if dom_name == "encode" else "read2_write1"
+    ceiling = ceiling_leg(tdct, torch, stream, names=(mix,))[mix]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
+            "stream_ceiling": {"mix": mix, "gbs": ceiling, "frac": round(achieved / ceiling, 4)},
             "kernel": "batch_kernel (%s), 64 x 4096^2, %d B/px algorithmic" % (dom_name, 3),
             "encode_ms": round(enc_avg, 4), "decode_ms": round(dec_avg, 4),
             "encode_gbs": round(bytes_launch / (enc_avg / 1e3) / 1e9, 1),
