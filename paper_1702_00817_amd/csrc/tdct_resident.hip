@@ -4,8 +4,8 @@
 //
 // Workgroup 0 is the front wave: it polls the host's published count, copies
 // each new job into device memory, cuts it into work items of one or more
-// tiles, fills the job's entries of the item ring and then publishes the
-// items with a release store. Every other workgroup is one worker wave: it
+// tiles and fills the job's entries of the item ring; the items of up to 32
+// jobs taken in one pass are then published behind one release. Every other workgroup is one worker wave: it
 // takes a ticket for the next item, waits until that item is published,
 // copies the item's job into its LDS, runs the encoder or decoder tiles of
 // the item (the same per-wave code as the batch kernel) and counts the item
@@ -26,6 +26,7 @@
 // wave issues no cache maintenance. Job data
 // written inside the kernel is read with lane-indexed loads and kept in LDS.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "tdct.h"
@@ -69,37 +70,56 @@ __device__ __forceinline__ T uniform_copy(const T* p) {
 // lanes around it and back into a polling loop whose exit only lane 0
 // decides.
 
+// Jobs the front wave copies in before it publishes their items together.
+constexpr uint32_t kIngestBatch = 32;
+
 __device__ void front_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0) {
     uint64_t taken = first_lane64(__hip_atomic_load(&a.st->taken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     uint64_t items = first_lane64(__hip_atomic_load(&a.st->items_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const uint32_t jmask = a.ring_jobs - 1, imask = a.ring_items - 1;
-    // lanes 36..63 all handle the job's last 16-byte chunk (same value, same place)
+    // lanes past the job's last 16-byte chunk all handle that chunk (same
+    // value, same place)
     const uint32_t k = lane < (uint32_t)kJobChunks ? lane : (uint32_t)kJobChunks - 1;
+    // chunk holding base (x, y), ntiles (z), done_value (w); then item_tiles (x)
+    constexpr uint32_t kCountChunk = (uint32_t)(offsetof(ResidentJob, base) / 16);
+    constexpr uint32_t kItemChunk = (uint32_t)(offsetof(ResidentJob, item_tiles) / 16);
+    static_assert(offsetof(ResidentJob, base) % 16 == 0 && offsetof(ResidentJob, item_tiles) % 16 == 0,
+                  "fields the front wave patches start their chunks");
     uint64_t last = t0;
     while (true) {
-        const uint64_t ctrl = first_lane64(__hip_atomic_load(a.ctrl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+        // relaxed: an idle poll costs no cache maintenance
+        const uint64_t ctrl = first_lane64(__hip_atomic_load(a.ctrl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
         const uint64_t now = ticks();
         if ((ctrl & kCtrlStop) || now - t0 > a.life_ticks) break;
-        if (taken < (ctrl & ~kCtrlStop)) {
-            const uint32_t slot = (uint32_t)taken & jmask;
-            v4u c = reinterpret_cast<const v4u*>(a.ring + slot)[k];
-            // last chunk: base (x, y), ntiles (z), done_value (w)
-            const uint32_t ntiles = (uint32_t)__shfl((int)c.z, kJobChunks - 1);
-            const uint32_t per = item_tiles(ntiles, a.workers);
-            uint32_t nitems = (ntiles + per - 1) / per;
-            nitems = nitems > a.ring_items ? a.ring_items : nitems;
-            const bool last_chunk = k == (uint32_t)kJobChunks - 1;
-            c.x = last_chunk ? (uint32_t)items : c.x;
-            c.y = last_chunk ? (uint32_t)(items >> 32) : c.y;
-            reinterpret_cast<v4u*>(a.jobs + slot)[k] = c;
-            a.remaining[slot] = nitems;
-            for (uint32_t i = lane; i < nitems; i += 64) a.item_slot[(uint32_t)(items + i) & imask] = slot;
-            // job copy, count and item entries before the items become visible
+        const uint64_t pub = ctrl & ~kCtrlStop;
+        if (taken < pub) {
+            // the host wrote these jobs before raising the count
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            const uint32_t n = pub - taken < kIngestBatch ? (uint32_t)(pub - taken) : kIngestBatch;
+            // items published and not yet handed out (negative while workers wait)
+            const uint64_t handed =
+                first_lane64(__hip_atomic_load(&a.st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            for (uint32_t j = 0; j < n; ++j) {
+                const uint32_t slot = (uint32_t)(taken + j) & jmask;
+                v4u c = reinterpret_cast<const v4u*>(a.ring + slot)[k];
+                const uint32_t ntiles = (uint32_t)__shfl((int)c.z, (int)kCountChunk);
+                const bool backlog = (int64_t)(items - handed) > (int64_t)a.workers;
+                const uint32_t per = item_tiles(ntiles, a.workers, backlog);
+                uint32_t nitems = (ntiles + per - 1) / per;
+                nitems = nitems > a.ring_items ? a.ring_items : nitems;
+                c.x = k == kCountChunk ? (uint32_t)items : (k == kItemChunk ? per : c.x);
+                c.y = k == kCountChunk ? (uint32_t)(items >> 32) : c.y;
+                reinterpret_cast<v4u*>(a.jobs + slot)[k] = c;
+                a.remaining[slot] = nitems;
+                for (uint32_t i = lane; i < nitems; i += 64) a.item_slot[(uint32_t)(items + i) & imask] = slot;
+                items += nitems;
+            }
+            // the job copies, counts and item entries before the items
+            // become visible
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            taken += 1;
-            items += nitems;
+            taken += n;
             __hip_atomic_store(&a.st->taken, taken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.st->items_pub, items, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.st->items_pub, items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             last = now;
             continue;
         }
@@ -204,7 +224,8 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
             cur_base = first_lane64(J->base);
             ntiles = __builtin_amdgcn_readfirstlane(J->ntiles);
             done_value = __builtin_amdgcn_readfirstlane(J->done_value);
-            per = item_tiles(ntiles, a.workers);
+            per = __builtin_amdgcn_readfirstlane(J->item_tiles);
+            per = per ? per : 1;
             cur_end = cur_base + (ntiles + per - 1) / per;
             tb = (uint32_t)tile_blocks(d.op);
         }

@@ -26,6 +26,8 @@ struct alignas(16) ResidentJob {
                          // of the job's first work item
     uint32_t ntiles;     // tiles of 128 (encoder ops) or 64 (decoder) blocks
     uint32_t done_value; // written to the job's done flag when it completes
+    uint32_t item_tiles; // device copy: tiles per work item, chosen by the front wave
+    uint32_t pad[3];
 };
 static_assert(sizeof(ResidentJob) % 16 == 0, "jobs are copied in 16-byte chunks");
 constexpr int kJobChunks = (int)(sizeof(ResidentJob) / 16);
@@ -61,11 +63,15 @@ struct ResidentArgs {
     uint64_t life_ticks;      // every wave exits after this long in any case
 };
 
-// Tiles per work item: one while a job has fewer than two tiles per worker,
-// so every worker can take part; more for larger jobs (at most 16), so that
-// the per-item synchronisation is paid once per several tiles.
+// Tiles per work item. While fewer items wait than there are workers, a job
+// gets one-tile items until it has two tiles per worker (so every worker can
+// take part and a small job finishes soon), and proportionally larger ones
+// above that. Under a backlog every job gets 16-tile items: parallelism then
+// comes from the queue, and the ticket counter, one atomic on one address
+// per item, is touched 16 times less often.
 constexpr uint32_t kMaxItemTiles = 16;
-__host__ __device__ inline uint32_t item_tiles(uint32_t ntiles, uint32_t workers) {
+__host__ __device__ inline uint32_t item_tiles(uint32_t ntiles, uint32_t workers, bool backlog) {
+    if (backlog) return ntiles < kMaxItemTiles ? (ntiles ? ntiles : 1) : kMaxItemTiles;
     const uint32_t c = ntiles / (2 * (workers ? workers : 1));
     return c < 1 ? 1 : (c > kMaxItemTiles ? kMaxItemTiles : c);
 }

@@ -686,6 +686,7 @@ void resident_publish(tdct_server* s, double now) {
         J.base = R.next_tile;
         J.ntiles = (uint32_t)nt;
         J.done_value = (uint32_t)(seq + 1);
+        J.item_tiles = 0;  // the kernel chooses
         R.live.push_back({t, seq, R.next_tile, (uint32_t)nt, (int32_t)R.live.size() + 1, false});
         R.next_seq++;
         R.next_tile += nt;
