@@ -137,6 +137,45 @@ __device__ __forceinline__ T* global_ptr(T* p) {
     return (T*)(GT*)(uintptr_t)p;
 }
 
+// Codes tiles [tile0, tile1) of one image. A lone worker wave is bound by
+// memory latency, so while it codes a tile it already loads the next one's
+// inputs (the tile code calls the hook once the current inputs are
+// consumed and before its stores).
+template <int OP>
+__device__ __forceinline__ void code_item(const ImgDesc& d, const QConst& qc, uint32_t tile0,
+                                          uint32_t tile1, uint32_t tb, uint32_t lane, v4u* wl) {
+    if (tile0 >= tile1) return;
+    const uint32_t nblk = (uint32_t)d.nblk;
+    uint32_t first = tile0 * tb, count = min(tb, nblk - first);
+    if constexpr (OP == OP_ENCODE) {
+        EncPixels P;
+        enc_load(d, first, count, lane, P);
+        for (uint32_t tile = tile0; tile < tile1; ++tile) {
+            const bool more = tile + 1 < tile1;
+            const uint32_t nfirst = first + tb;
+            const uint32_t ncount = more ? min(tb, nblk - nfirst) : 0u;
+            enc_tile<OP_ENCODE>(d, qc, first, count, lane, wl, P, [&]() {
+                if (more) enc_load(d, nfirst, ncount, lane, P);
+            });
+            first = nfirst;
+            count = ncount;
+        }
+    } else {
+        DecChunks C;
+        dec_load(d, first, count, lane, C);
+        for (uint32_t tile = tile0; tile < tile1; ++tile) {
+            const bool more = tile + 1 < tile1;
+            const uint32_t nfirst = first + tb;
+            const uint32_t ncount = more ? min(tb, nblk - nfirst) : 0u;
+            dec_tile(d, qc, first, count, lane, wl, C, [&]() {
+                if (more) dec_load(d, nfirst, ncount, lane, C);
+            });
+            first = nfirst;
+            count = ncount;
+        }
+    }
+}
+
 // 1 once item t is published, 2 when the wave should leave holding t;
 // `pub` receives the published count seen.
 __device__ __forceinline__ uint32_t ticket_state(const ResidentArgs& a, uint64_t t, uint64_t t0, uint64_t& pub) {
@@ -229,17 +268,13 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
             cur_end = cur_base + (ntiles + per - 1) / per;
             tb = (uint32_t)tile_blocks(d.op);
         }
-        const uint64_t tile0 = (t - cur_base) * per;
-        const uint64_t tile1 = min(tile0 + per, (uint64_t)ntiles);
-        for (uint64_t tile = tile0; tile < tile1; ++tile) {
-            const uint64_t first = tile * tb;
-            if (first >= (uint64_t)d.nblk) break;
-            const uint32_t count = (uint32_t)min((uint64_t)tb, (uint64_t)d.nblk - first);
-            if (d.op == OP_ENCODE)
-                run_tile<OP_ENCODE>(d, J->qc, (uint32_t)first, count, lane, wl);
-            else if (d.op == OP_DECODE)
-                run_tile<OP_DECODE>(d, J->qc, (uint32_t)first, count, lane, wl);
-        }
+        const uint64_t tmax = ((uint64_t)d.nblk + tb - 1) / tb;
+        const uint32_t tile0 = (uint32_t)min((t - cur_base) * per, tmax);
+        const uint32_t tile1 = (uint32_t)min((uint64_t)tile0 + per, min((uint64_t)ntiles, tmax));
+        if (d.op == OP_ENCODE)
+            code_item<OP_ENCODE>(d, J->qc, tile0, tile1, tb, lane, wl);
+        else if (d.op == OP_DECODE)
+            code_item<OP_DECODE>(d, J->qc, tile0, tile1, tb, lane, wl);
         pend_slot = slot;
         pend_done = done_value;
         if (++pend_items >= kMaxPendingItems) count_off();

@@ -100,10 +100,9 @@ __device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint3
 }
 
 // Loads the run of 512 chunks at src (only its first nchunks; the rest read
-// as zero) and hands every lane the 8 chunks of its own int16 block.
-__device__ __forceinline__ void stage_in(v4u* wl, const v4u* src, uint32_t nchunks, uint32_t lane,
-                                         v4u (&mine)[8]) {
-    v4u tmp[8];
+// as zero): chunk 64 k + lane into tmp[k].
+__device__ __forceinline__ void stage_load(const v4u* src, uint32_t nchunks, uint32_t lane,
+                                           v4u (&tmp)[8]) {
     if (nchunks == 512) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) tmp[k] = ld_nt4(src + 64u * k + lane);
@@ -114,6 +113,11 @@ __device__ __forceinline__ void stage_in(v4u* wl, const v4u* src, uint32_t nchun
             tmp[k] = c < nchunks ? ld_nt4(src + c) : (v4u){0u, 0u, 0u, 0u};
         }
     }
+}
+
+// Hands every lane the 8 chunks of its own int16 block from a loaded run.
+__device__ __forceinline__ void stage_swap(v4u* wl, const v4u (&tmp)[8], uint32_t lane,
+                                           v4u (&mine)[8]) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint32_t c = 64u * k + lane;
@@ -215,31 +219,52 @@ __device__ __forceinline__ void decode_block(const uint32_t (&qp)[32], const QC&
 // 512-byte run, and the coefficients of all a-blocks (then all b-blocks) are
 // one contiguous 8 KB run for the staged stores.
 
-template <int OP, class QC>
-__device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
-                                         uint32_t count, uint32_t lane, v4u* wl) {
+// Raw pixel rows of an encoder tile as loaded: rows of block first + l (A)
+// and of block first + 64 + l (B).
+struct EncPixels {
+    uint32_t A[8][2], B[8][2];
+};
+
+__device__ __forceinline__ void enc_load(const ImgDesc& d, uint32_t first, uint32_t count,
+                                         uint32_t lane, EncPixels& P) {
     const bool va = lane < count, vb = lane + 64u < count;
     const uint32_t nbx = (uint32_t)d.nbx;
     const uint32_t ba = first + lane, bb = ba + 64u;
-
-    uint32_t A[8][2], B[8][2];
     if (count == (uint32_t)kEncTileBlocks && (d.flags & F_SRC8)) {
         const uint8_t* pa = d.src + block_offset(d.src_stride, nbx, ba);
         const uint8_t* pb = d.src + block_offset(d.src_stride, nbx, bb);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const v2u x = ld_nt2(pa + r * d.src_stride), y = ld_nt2(pb + r * d.src_stride);
-            A[r][0] = x.x;
-            A[r][1] = x.y;
-            B[r][0] = y.x;
-            B[r][1] = y.y;
+            P.A[r][0] = x.x;
+            P.A[r][1] = x.y;
+            P.B[r][0] = y.x;
+            P.B[r][1] = y.y;
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) A[r][0] = A[r][1] = B[r][0] = B[r][1] = 0x80808080u;
-        if (va) load_rows8(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, A);
-        if (vb) load_rows8(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, B);
+        for (int r = 0; r < 8; ++r) P.A[r][0] = P.A[r][1] = P.B[r][0] = P.B[r][1] = 0x80808080u;
+        if (va) load_rows8(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, P.A);
+        if (vb) load_rows8(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, P.B);
     }
+}
+
+// A hook the tile code calls once its inputs are consumed and before its
+// stores (a caller walking several tiles loads the next one's inputs there).
+struct NoPrefetch {
+    __device__ void operator()() const {}
+};
+
+// Codes the tile whose pixels are in P.
+template <int OP, class QC, class PF>
+__device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, uint32_t lane, v4u* wl, EncPixels& P,
+                                         PF&& prefetch) {
+    const bool va = lane < count, vb = lane + 64u < count;
+    const uint32_t nbx = (uint32_t)d.nbx;
+    const uint32_t ba = first + lane, bb = ba + 64u;
+    const auto& A = P.A;
+    const auto& B = P.B;
 
     // Pixel (r, c) of both blocks as a packed (a, b) int16 pair.
     s16x2 v[64];
@@ -252,6 +277,7 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
             v[8 * r + c] = as_s16x2(__builtin_amdgcn_perm(B[r][c >> 2], A[r][c >> 2], sel));
         }
     }
+    prefetch();
     fwd8x8(v);
     v[0] -= (s16x2){8192, 8192};
 
@@ -356,16 +382,33 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
     }
 }
 
+template <int OP, class QC>
+__device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, uint32_t lane, v4u* wl) {
+    EncPixels P;
+    enc_load(d, first, count, lane, P);
+    enc_tile<OP>(d, qc, first, count, lane, wl, P, NoPrefetch());
+}
+
 // ---- decoder tile -----------------------------------------------------------
 //
 // Lane l owns block first + l.
 
+// The tile's coefficients as loaded: 16-byte chunk 64 k + l of the tile's run
+// in element k of lane l.
+struct DecChunks {
+    v4u c[8];
+};
+
+__device__ __forceinline__ void dec_load(const ImgDesc& d, uint32_t first, uint32_t count,
+                                         uint32_t lane, DecChunks& C) {
+    stage_load(reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, C.c);
+}
+
+// Decodes lane's block from its 8 chunks and stores its pixels.
 template <class QC>
-__device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
-                                         uint32_t count, uint32_t lane, v4u* wl) {
-    v4u mine[8];
-    stage_in(wl, reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, mine);
-    if (lane >= count) return;
+__device__ __forceinline__ void dec_finish(const ImgDesc& d, const QC& qc, uint32_t first,
+                                           uint32_t lane, const v4u (&mine)[8]) {
     uint32_t qp[32];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -378,6 +421,27 @@ __device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_
     decode_block(qp, qc, px);
     const uint32_t b = first + lane;
     store_rows8(d.dst + block_offset(d.dst_stride, (uint32_t)d.nbx, b), d.dst_stride, d.flags, px);
+}
+
+template <class QC, class PF>
+__device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, uint32_t lane, v4u* wl, DecChunks& C,
+                                         PF&& prefetch) {
+    v4u mine[8];
+    stage_swap(wl, C.c, lane, mine);
+    prefetch();
+    if (lane >= count) return;
+    dec_finish(d, qc, first, lane, mine);
+}
+
+template <class QC>
+__device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
+                                         uint32_t count, uint32_t lane, v4u* wl) {
+    v4u tmp[8], mine[8];
+    stage_load(reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, tmp);
+    stage_swap(wl, tmp, lane, mine);
+    if (lane >= count) return;
+    dec_finish(d, qc, first, lane, mine);
 }
 
 template <int OP, class QC>
