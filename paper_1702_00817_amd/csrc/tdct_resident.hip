@@ -5,14 +5,14 @@
 // Workgroup 0 is the front wave: it polls the host's published count, copies
 // each new job into device memory, cuts it into work items of one or more
 // tiles and fills the job's entries of the item ring; the items of up to 32
-// jobs taken in one pass are then published behind one release. Every other workgroup is one worker wave: it
-// takes a ticket for the next item, waits until that item is published,
-// copies the item's job into its LDS, runs the encoder or decoder tiles of
-// the item (the same per-wave code as the batch kernel) and counts the item
-// off (a wave that keeps getting items of one job counts them off together,
-// before it waits, changes job or holds 8); the wave that finishes a job's
-// last item writes the job's done flag into host memory with a system-scope
-// release.
+// jobs taken in one pass are then published behind one release. Every other
+// workgroup is one worker wave: it takes a ticket for the next item, waits
+// until that item is published, copies the item's job into its LDS (unless
+// it already holds that job), runs the encoder or decoder tiles of the item
+// (the per-wave tile code of the batch kernel) and counts the item off. A
+// wave that keeps getting items of one job counts them off together, before
+// it waits, changes job or holds 8. The wave that finishes a job's last item
+// writes the job's done flag into host memory with a system-scope release.
 //
 // Every wave has an exit that it always reaches: the front wave leaves when
 // the host sets the stop bit, after idle_ticks without a new job or after
@@ -23,8 +23,8 @@
 //
 // Synchronisation uses only vector memory operations: scoped atomic loads,
 // stores and fetch-adds, plus fences; polling loads are relaxed, so an idle
-// wave issues no cache maintenance. Job data
-// written inside the kernel is read with lane-indexed loads and kept in LDS.
+// wave issues no cache maintenance. Job data written inside the kernel is
+// read with lane-indexed loads and kept in LDS.
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
