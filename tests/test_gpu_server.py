@@ -235,3 +235,39 @@ def test_resident_kernel_relaunches_after_idle_exit(tdct):
         assert tdct.tdct_server_last_error(srv) == ""
     finally:
         tdct.tdct_server_destroy(srv)
+
+
+def test_resident_large_and_ragged_requests(tdct):
+    """Requests big enough for multi-tile work items on few workers (so the
+    in-item prefetch runs), with odd block counts per row and partial last
+    tiles, encode and decode, each equal to the oracle in full."""
+    import torch
+    hip = _hip()
+    rng = np.random.default_rng(60)
+    cases = []
+    for k, (w, h) in enumerate([(4104, 1032), (2048, 2056), (1032, 4104), (3000, 8)]):
+        img = synth.textured(w, h, 8000 + k)
+        Q = synth.qtable(1, 1 + k)
+        nblk = (w // 8) * (h // 8)
+        coefs = rng.integers(-2000, 2001, size=(nblk, 64)).astype(np.int16)
+        cases.append((w, h, img, Q, coefs, torch.from_numpy(img).cuda(), torch.from_numpy(coefs).cuda()))
+    for workers in (3, 16):
+        srv = tdct.tdct_server_create(tdct.server_cfg(1 << 30, resident=1, resident_workers=workers,
+                                                      resident_idle_us=5000))
+        try:
+            tickets = []
+            for w, h, img, Q, coefs, dimg, dcoef in cases:
+                tickets.append(tdct.tdct_server_submit(srv, tdct.request(tdct.OP_ENCODE, w, h, dimg, Q, keep=40)))
+                tickets.append(tdct.tdct_server_submit(srv, tdct.request(tdct.OP_DECODE, w, h, dcoef, Q)))
+            for k, (w, h, img, Q, coefs, _, _) in enumerate(cases):
+                r = tdct.tdct_server_wait(srv, tickets[2 * k])
+                assert r.status == tdct.TDCT_OK
+                got = _read(hip, r.output, r.output_bytes).view(np.int16).reshape(-1, 64)
+                assert np.array_equal(got, O.quantise(img, Q, 40, threads=8)), (workers, w, h, "encode")
+                r = tdct.tdct_server_wait(srv, tickets[2 * k + 1])
+                assert r.status == tdct.TDCT_OK
+                got = _read(hip, r.output, r.output_bytes).reshape(h, w)
+                assert np.array_equal(got, O.inverse(coefs, Q, w, h, threads=8)), (workers, w, h, "decode")
+            assert tdct.tdct_server_last_error(srv) == ""
+        finally:
+            tdct.tdct_server_destroy(srv)
