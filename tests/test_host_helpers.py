@@ -74,7 +74,7 @@ def test_butterflies_equal_dense_T_on_all_3pow8_vectors(hc, oracle_mod):
 
 def test_butterflies_equal_dense_T_on_random_int16(hc, oracle_mod):
     rng = np.random.default_rng(21)
-    V = rng.integers(-32768, 32768, size=(200000, 8))
+    V = rng.integers(-32768, 32768, size=(1_000_000, 8))
     T = oracle_mod.T().astype(np.int64)
     assert np.array_equal(_apply8(hc, V, 0), V @ T.T)
     assert np.array_equal(_apply8(hc, V, 1), V @ T)
