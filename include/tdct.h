@@ -213,12 +213,15 @@ typedef struct {
     int32_t fake_fail_every; /* fake device only: every n-th batch fails (0 = never) */
     /* Resident mode (resident = 1): no launch per batch. Requests go into a
      * queue in host-coherent pinned memory that a resident kernel polls; its
-     * front wave copies each request to the device and cuts it into tiles,
-     * its worker waves claim tiles from a device-side ring and code them, and
-     * the wave that finishes a request's last tile raises the request's done
-     * flag in host memory, which the scheduler polls. The kernel exits after
-     * resident_idle_us without a new request (and after one second in any
-     * case) and is relaunched by the next one. streams, max_batch,
+     * front wave copies each request to the device and cuts it into work
+     * items of one or more tiles, its worker waves take items from a
+     * device-side ring and code them, and the wave that finishes a request's
+     * last item raises the request's done flag in host memory, which the
+     * scheduler polls. Submitting a request publishes it at once from the
+     * submitting thread. The kernel exits after resident_idle_us without a
+     * new request (and after one second in any case) and is relaunched by
+     * the next one; while requests are live, the next launch is queued behind
+     * the running one before its second ends. streams, max_batch,
      * max_wait_us, batching, max_batch_px and tune are unused; host_io
      * requests are refused (TDCT_EINVAL). With fake_device_us > 0 a host
      * thread plays the kernel's part of the protocol. */
@@ -228,9 +231,10 @@ typedef struct {
     int32_t resident_idle_us; /* 0: 20000 */
     int32_t resident_jobs;    /* queue slots, rounded up to a power of two (0: 1024,
                                  at most 65536); a request holds its slot until done */
-    int32_t resident_tiles;   /* tile-ring slots, rounded up to a power of two (0: 2^21,
-                                 at most 2^24); a request with more tiles than this
-                                 (blocks / 128 encoding, blocks / 64 decoding) is
+    int32_t resident_tiles;   /* work-item ring slots, rounded up to a power of two
+                                 (0: 2^21, at most 2^24); a request with more tiles
+                                 than this (blocks / 128 encoding, blocks / 64
+                                 decoding; an item holds one or more tiles) is
                                  refused with TDCT_ENOMEM */
     int32_t resident_reserved;
 } tdct_server_cfg;

@@ -235,11 +235,13 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
             count_off();  // nothing else to do meanwhile
             uint32_t backoff = 1;
             while (state == 0) {
-                // waves far down the queue poll less often
+                // the next waves in the queue poll often; waves far down it
+                // less
                 const uint64_t ahead = t - pub;
+                const uint32_t cap = ahead < 32 ? 2u : 8u;
                 const uint32_t far = ahead > 32 * 32 ? 32u : (uint32_t)(ahead / 32);
                 nap(backoff > far ? backoff : far);
-                backoff = backoff < 8 ? 2 * backoff : 8;
+                backoff = backoff < cap ? 2 * backoff : cap;
                 state = ticket_state(a, t, t0, pub);
             }
             if (state == 2) break;

@@ -136,6 +136,8 @@ struct Resident {
     ResidentArgs args{};
     uint32_t epoch = 0;
     bool running = false;  // a launch may still be on the device
+    double queried_us = -1e30;  // last time the launch's stream was queried
+    double started_us = 0;      // when the newest launch started (or is expected to)
     uint64_t next_seq = 0, next_tile = 0;
     double stop_us = -1;  // when shutdown found requests still live
     struct Live {
@@ -404,11 +406,44 @@ void finish_request(tdct_server* s, uint64_t t, int status, int batch_size, doub
     }
 }
 
+// Admission: waiting requests, oldest first, reserve their arena bytes; the
+// first that does not fit stops admission. Lock held.
+void admit(tdct_server* s, double now, bool any_busy) {
+    while (!s->waiting.empty()) {
+        Req& q = s->reqs[s->waiting.front()];
+        const int64_t off = s->arena->alloc(reserve_bytes(q.r));
+        if (off < 0) {
+            // Shutting down with nothing left in flight: the memory this
+            // request waits for is held by outputs the client never
+            // released, so it can never be admitted.
+            if (s->stop && !any_busy && s->admitted.empty()) {
+                const uint64_t t = s->waiting.front();
+                s->waiting.pop_front();
+                finish_request(s, t, TDCT_EBUSY, 0, now);
+                s->done.notify_all();
+                continue;
+            }
+            break;
+        }
+        q.arena_off = off;
+        s->last_activity_us = now;
+        s->admitted.push_back(s->waiting.front());
+        s->waiting.pop_front();
+    }
+    s->st.arena_bytes_in_use = s->arena->used();
+    s->st.arena_high_water = s->arena->high();
+}
+
 // How long the scheduler keeps polling after the last activity before it
 // sleeps on its condition variable.
 constexpr double kSpinUs = 2000.0;
 
 // ---- resident mode -------------------------------------------------------
+
+// Lifetime of one launch of the resident kernel, and how long before its end
+// the next launch is queued behind it while requests are live.
+constexpr double kLifeUs = 1e6;
+constexpr double kAheadUs = 5e4;
 
 void fake_error(tdct_server* s, const char* what) {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -542,7 +577,7 @@ int resident_init(tdct_server* s) {
     a.ring_items = R.ring_tiles;
     a.workers = (uint32_t)R.workers;
     a.idle_ticks = (uint64_t)(R.idle_us * (double)khz / 1000.0);
-    a.life_ticks = (uint64_t)khz * 1000;  // one second
+    a.life_ticks = (uint64_t)(kLifeUs * (double)khz / 1000.0);
     return TDCT_OK;
 }
 
@@ -563,39 +598,70 @@ void resident_free(tdct_server* s) {
     R.stream = nullptr;
 }
 
-// Starts the kernel (or its host stand-in). Lock held.
-int resident_launch(tdct_server* s) {
+// Queues one launch of the kernel on its stream; it starts once the launch
+// before it (if any) has ended. Lock held.
+int resident_enqueue(tdct_server* s) {
     Resident& R = s->res;
     R.epoch++;
     s->batches++;
+    R.args.epoch = R.epoch;
+    if (R.epoch > 1) {
+        // Tickets the last launch's workers left with are beyond its last
+        // published work item; start handing out tickets from there again.
+        hipError_t e = hipMemcpyAsync(&R.args.st->cursor, &R.args.st->items_pub, sizeof(uint64_t),
+                                      hipMemcpyDeviceToDevice, R.stream);
+        if (e != hipSuccess) {
+            set_error("resident cursor rewind", e);
+            return TDCT_EDEVICE;
+        }
+    }
+    return launch_resident(R.args, R.workers, R.stream);
+}
+
+// Starts the kernel (or its host stand-in) when no launch is live. Lock held.
+int resident_launch(tdct_server* s, double now) {
+    Resident& R = s->res;
     if (s->fake) {
+        R.epoch++;
+        s->batches++;
         if (R.fake.joinable()) R.fake.join();  // its loop has ended: fake_live was false
         R.fake_live.store(true, std::memory_order_release);
         R.fake = std::thread(fake_resident, s);
     } else {
-        R.args.epoch = R.epoch;
-        if (R.epoch > 1) {
-            // Tickets the last launch's workers left with are beyond its last
-            // published work item; start handing out tickets from there again.
-            hipError_t e = hipMemcpyAsync(&R.args.st->cursor, &R.args.st->items_pub, sizeof(uint64_t),
-                                          hipMemcpyDeviceToDevice, R.stream);
-            if (e != hipSuccess) {
-                set_error("resident cursor rewind", e);
-                return TDCT_EDEVICE;
-            }
-        }
-        int st = launch_resident(R.args, R.workers, R.stream);
+        int st = resident_enqueue(s);
         if (st) return st;
     }
     R.running = true;
+    R.started_us = now;
     return TDCT_OK;
+}
+
+// A launch ends after its lifetime even under load; shortly before that,
+// the next one is queued behind it, so it starts the moment the old one
+// exits and requests see no gap. Lock held.
+void resident_keep_alive(tdct_server* s, double now) {
+    Resident& R = s->res;
+    if (s->fake || !R.running || R.live.empty() || now - R.started_us < kLifeUs - kAheadUs) return;
+    if (resident_enqueue(s) == TDCT_OK) {
+        R.started_us += kLifeUs;  // expected start: when the running launch reaches its lifetime
+    } else {
+        memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
+        R.started_us = now;  // retried a lifetime later; the live launch still serves meanwhile
+    }
 }
 
 // Step 1 in resident mode: notices the end of a launch, retires requests
 // whose done flag is up. Returns whether requests are still live. Lock held.
+// The kernel only ends after resident_idle_us without a request, after its
+// lifetime or on the stop bit, so its stream is queried at most every
+// kQueryUs (a runtime call on every pass would slow the polling of the done
+// flags).
+constexpr double kQueryUs = 100.0;
+
 bool resident_completions(tdct_server* s, double now) {
     Resident& R = s->res;
-    if (R.running) {
+    if (R.running && (s->fake || now - R.queried_us >= kQueryUs)) {
+        R.queried_us = now;
         bool ended;
         int status = TDCT_OK;
         if (s->fake) {
@@ -696,7 +762,7 @@ void resident_publish(tdct_server* s, double now) {
     }
     if (published) s->last_activity_us = now;
     if (!R.live.empty() && !R.running) {
-        const int st = resident_launch(s);
+        const int st = resident_launch(s, now);
         if (st) {
             memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
             for (Resident::Live& L : R.live)
@@ -743,6 +809,7 @@ void scheduler(tdct_server* s) {
         if (s->cfg.resident) {
             if (s->stop) resident_shutdown_watchdog(s, now);
             any_busy |= resident_completions(s, now);
+            resident_keep_alive(s, now);
         }
         if (any_busy) {
             if (s->busy_since < 0) s->busy_since = now;
@@ -751,29 +818,7 @@ void scheduler(tdct_server* s) {
             s->busy_since = -1;
         }
         // 2. admission, FIFO
-        while (!s->waiting.empty()) {
-            Req& q = s->reqs[s->waiting.front()];
-            const int64_t off = s->arena->alloc(reserve_bytes(q.r));
-            if (off < 0) {
-                // Shutting down with nothing left in flight: the memory this
-                // request waits for is held by outputs the client never
-                // released, so it can never be admitted.
-                if (s->stop && !any_busy && s->admitted.empty()) {
-                    const uint64_t t = s->waiting.front();
-                    s->waiting.pop_front();
-                    finish_request(s, t, TDCT_EBUSY, 0, now);
-                    s->done.notify_all();
-                    continue;
-                }
-                break;
-            }
-            q.arena_off = off;
-            s->last_activity_us = now;
-            s->admitted.push_back(s->waiting.front());
-            s->waiting.pop_front();
-        }
-        s->st.arena_bytes_in_use = s->arena->used();
-        s->st.arena_high_water = s->arena->high();
+        admit(s, now, any_busy);
         // 3. launches
         double next_deadline = -1;
         if (s->cfg.resident) resident_publish(s, now);
@@ -942,6 +987,13 @@ static int submit_locked(tdct_server* s, const tdct_request* req, bool release_o
     s->in_flight++;
     s->st.submitted++;
     *ticket = t;
+    if (s->cfg.resident) {
+        // Resident mode: admit and publish right here, so a sleeping
+        // scheduler's wake-up overlaps the kernel's work instead of
+        // preceding it (the scheduler still watches the done flags).
+        admit(s, q.submit_us, true);
+        resident_publish(s, q.submit_us);
+    }
     return TDCT_OK;
 }
 
