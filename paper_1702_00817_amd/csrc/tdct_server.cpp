@@ -434,6 +434,63 @@ void admit(tdct_server* s, double now, bool any_busy) {
     s->st.arena_high_water = s->arena->high();
 }
 
+// Step 3 of the scheduler: launches admitted requests on free stream slots
+// (up to max_batch and max_batch_px per launch, after the batching window).
+// Unlocks `lk` around each launch; only the scheduler thread launches, so no
+// completion step runs meanwhile. Returns the end of a pending batching
+// window, or -1.
+double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
+                   std::vector<BatchItem>& items) {
+    double next_deadline = -1;
+    for (Slot& sl : s->slots) {
+        if (sl.busy || s->admitted.empty()) continue;
+        const int maxb = s->cfg.batching ? std::max(1, s->cfg.max_batch) : 1;
+        const double oldest = s->reqs[s->admitted.front()].submit_us;
+        if (s->cfg.batching && s->cfg.max_wait_us > 0 && (int)s->admitted.size() < maxb &&
+            now - oldest < s->cfg.max_wait_us && !s->stop) {
+            next_deadline = oldest + s->cfg.max_wait_us;
+            break;
+        }
+        items.clear();
+        int64_t batch_px = 0;
+        while (!s->admitted.empty() && (int)items.size() < maxb) {
+            const uint64_t t = s->admitted.front();
+            Req& q = s->reqs[t];
+            const int64_t px = (int64_t)q.r.w * q.r.h;
+            if (!items.empty() && s->cfg.max_batch_px > 0 && batch_px + px > s->cfg.max_batch_px)
+                break;
+            batch_px += px;
+            s->admitted.pop_front();
+            char* base = s->arena_base + q.arena_off;
+            items.push_back({t, q.r, base,
+                             q.r.host_io ? base + Arena::round(q.out_bytes) : nullptr});
+            sl.tickets.push_back(t);
+        }
+        sl.busy = true;
+        s->last_activity_us = now;
+        s->batches++;
+        s->batch_reqs += (int64_t)items.size();
+        sl.launched_us = now;
+        if (s->fake) {
+            sl.fake_done_us = s->now_us() + s->cfg.fake_device_us;
+            sl.fake_fail = s->cfg.fake_fail_every > 0 && (s->batches % s->cfg.fake_fail_every) == 0;
+        }
+        lk.unlock();
+        const int st = launch_batch_on_slot(s, sl, items);
+        lk.lock();
+        if (st) {
+            memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
+            const double t_now = s->now_us();
+            const int bs = (int)sl.tickets.size();
+            for (uint64_t t : sl.tickets) finish_request(s, t, st, bs, t_now);
+            sl.tickets.clear();
+            sl.busy = false;
+            s->done.notify_all();
+        }
+    }
+    return next_deadline;
+}
+
 // How long the scheduler keeps polling after the last activity before it
 // sleeps on its condition variable.
 constexpr double kSpinUs = 2000.0;
@@ -820,54 +877,8 @@ void scheduler(tdct_server* s) {
         // 2. admission, FIFO
         admit(s, now, any_busy);
         // 3. launches
-        double next_deadline = -1;
         if (s->cfg.resident) resident_publish(s, now);
-        for (Slot& sl : s->slots) {
-            if (sl.busy || s->admitted.empty()) continue;
-            const int maxb = s->cfg.batching ? std::max(1, s->cfg.max_batch) : 1;
-            const double oldest = s->reqs[s->admitted.front()].submit_us;
-            if (s->cfg.batching && s->cfg.max_wait_us > 0 && (int)s->admitted.size() < maxb &&
-                now - oldest < s->cfg.max_wait_us && !s->stop) {
-                next_deadline = oldest + s->cfg.max_wait_us;
-                break;
-            }
-            items.clear();
-            int64_t batch_px = 0;
-            while (!s->admitted.empty() && (int)items.size() < maxb) {
-                const uint64_t t = s->admitted.front();
-                Req& q = s->reqs[t];
-                const int64_t px = (int64_t)q.r.w * q.r.h;
-                if (!items.empty() && s->cfg.max_batch_px > 0 && batch_px + px > s->cfg.max_batch_px)
-                    break;
-                batch_px += px;
-                s->admitted.pop_front();
-                char* base = s->arena_base + q.arena_off;
-                items.push_back({t, q.r, base,
-                                 q.r.host_io ? base + Arena::round(q.out_bytes) : nullptr});
-                sl.tickets.push_back(t);
-            }
-            sl.busy = true;
-            s->last_activity_us = now;
-            s->batches++;
-            s->batch_reqs += (int64_t)items.size();
-            sl.launched_us = now;
-            lk.unlock();
-            const int st = launch_batch_on_slot(s, sl, items);
-            lk.lock();
-            if (s->fake) {
-                sl.fake_done_us = s->now_us() + s->cfg.fake_device_us;
-                sl.fake_fail = s->cfg.fake_fail_every > 0 && (s->batches % s->cfg.fake_fail_every) == 0;
-            }
-            if (st) {
-                memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
-                const double t_now = s->now_us();
-                const int bs = (int)sl.tickets.size();
-                for (uint64_t t : sl.tickets) finish_request(s, t, st, bs, t_now);
-                sl.tickets.clear();
-                sl.busy = false;
-                s->done.notify_all();
-            }
-        }
+        const double next_deadline = launch_step(s, lk, now, items);
         if (s->stop && s->in_flight == 0) break;
         // While batches are in flight, or shortly after any activity, poll:
         // event completion and new arrivals are seen within microseconds.
@@ -997,17 +1008,25 @@ static int submit_locked(tdct_server* s, const tdct_request* req, bool release_o
     return TDCT_OK;
 }
 
-int tdct_server_submit(tdct_server* s, const tdct_request* req, uint64_t* ticket) {
-    if (!s || !req || !ticket) return TDCT_EINVAL;
-    int st = validate_for(s, *req);
-    if (st) return st;
+// Submits under the lock (in resident mode this also publishes the request)
+// and wakes the scheduler.
+static int submit_now(tdct_server* s, const tdct_request* req, bool release_on_done,
+                      uint64_t* ticket) {
+    int st;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return TDCT_EBUSY;
-        st = submit_locked(s, req, false, ticket);
+        st = submit_locked(s, req, release_on_done, ticket);
     }
-    if (st == TDCT_OK) s->wake.notify_one();
+    s->wake.notify_one();
     return st;
+}
+
+int tdct_server_submit(tdct_server* s, const tdct_request* req, uint64_t* ticket) {
+    if (!s || !req || !ticket) return TDCT_EINVAL;
+    const int st = validate_for(s, *req);
+    if (st) return st;
+    return submit_now(s, req, false, ticket);
 }
 
 static void fill_result(const tdct_server* s, const Req& q, tdct_result* out) {
@@ -1147,11 +1166,7 @@ int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* a
             if (left > std::chrono::microseconds(200))
                 std::this_thread::sleep_for(left - std::chrono::microseconds(100));
         }
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            sub[k] = submit_locked(s, &reqs[k], !keep_outputs, &tk[k]);
-        }
-        s->wake.notify_one();
+        sub[k] = submit_now(s, &reqs[k], !keep_outputs, &tk[k]);
     }
     tdct_server_drain(s);
     std::lock_guard<std::mutex> lk(s->mu);
