@@ -97,8 +97,8 @@ int validate_image(const tdct_image_desc& im, int32_t nq) {
 }
 
 void free_graph(tdct_plan* p) {
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
 }
@@ -207,7 +207,7 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
         e = hipMemcpy(p->qcs_d, p->qcs.data(), p->qcs.size() * sizeof(QConst), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         set_error("plan upload", e);
-        hipFree(p->dev);
+        (void)hipFree(p->dev);
         delete p;
         return TDCT_EDEVICE;
     }
@@ -240,7 +240,7 @@ int tdct_batch_graph(tdct_plan* p, void* stream) {
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(p->capture_stream, &g);
         if (st) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return st;
         }
         if (e != hipSuccess) {
@@ -269,7 +269,7 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return TDCT_EDEVICE;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return TDCT_EDEVICE;
     }
     const tdct_tune saved = p->tune;
@@ -294,17 +294,17 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
                 if ((st = run(p, s))) goto done;  // warm-up
                 std::vector<float> ms;
                 for (int r = 0; r < reps; ++r) {
-                    hipEventRecord(e0, s);
-                    if ((st = run(p, s))) goto done;
-                    hipEventRecord(e1, s);
-                    hipError_t e = hipEventSynchronize(e1);
+                    hipError_t e = hipEventRecord(e0, s);
+                    if (e == hipSuccess && (st = run(p, s))) goto done;
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float m = 0;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
                     if (e != hipSuccess) {
-                        set_error("autotune sync", e);
+                        set_error("autotune timing", e);
                         st = TDCT_EDEVICE;
                         goto done;
                     }
-                    float m = 0;
-                    hipEventElapsedTime(&m, e0, e1);
                     ms.push_back(m);
                 }
                 std::sort(ms.begin(), ms.end());
@@ -315,8 +315,8 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
                 }
             }
 done:
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st) {
         p->tune = saved;
         return st;
@@ -341,8 +341,8 @@ int tdct_plan_info_get(const tdct_plan* p, tdct_plan_info* out) {
 void tdct_plan_free(tdct_plan* p) {
     if (!p) return;
     free_graph(p);
-    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
-    if (p->dev) hipFree(p->dev);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->dev) (void)hipFree(p->dev);
     delete p;
 }
 

@@ -241,7 +241,7 @@ int ensure_capacity(tdct_server* s, Slot& sl, size_t bytes) {
     if (s->fake) return TDCT_OK;
     if (bytes > sl.dev_cap) {
         size_t cap = std::max(bytes, sl.dev_cap * 2);
-        if (sl.dev) hipFree(sl.dev);
+        if (sl.dev) (void)hipFree(sl.dev);
         sl.dev = nullptr;
         sl.dev_cap = 0;
         hipError_t e = hipMalloc(&sl.dev, cap);
@@ -253,7 +253,7 @@ int ensure_capacity(tdct_server* s, Slot& sl, size_t bytes) {
     }
     if (bytes > sl.pinned_cap) {
         size_t cap = std::max(bytes, sl.pinned_cap * 2);
-        if (sl.pinned) hipHostFree(sl.pinned);
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
         sl.pinned = nullptr;
         sl.pinned_cap = 0;
         hipError_t e = hipHostMalloc(&sl.pinned, cap, hipHostMallocDefault);
@@ -645,11 +645,11 @@ void resident_free(tdct_server* s) {
         free(R.host);
     } else {
         if (R.stream) {
-            hipStreamSynchronize(R.stream);
-            hipStreamDestroy(R.stream);
+            (void)hipStreamSynchronize(R.stream);
+            (void)hipStreamDestroy(R.stream);
         }
-        if (R.dev) hipFree(R.dev);
-        if (R.host) hipHostFree(R.host);
+        if (R.dev) (void)hipFree(R.dev);
+        if (R.host) (void)hipHostFree(R.host);
     }
     R.host = R.dev = nullptr;
     R.stream = nullptr;
@@ -952,12 +952,12 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
         if (e != hipSuccess) {
             set_error("server create", e);
             for (Slot& sl : s->slots) {
-                if (sl.done) hipEventDestroy(sl.done);
-                if (sl.stream) hipStreamDestroy(sl.stream);
-                if (sl.dev) hipFree(sl.dev);
-                if (sl.pinned) hipHostFree(sl.pinned);
+                if (sl.done) (void)hipEventDestroy(sl.done);
+                if (sl.stream) (void)hipStreamDestroy(sl.stream);
+                if (sl.dev) (void)hipFree(sl.dev);
+                if (sl.pinned) (void)hipHostFree(sl.pinned);
             }
-            if (s->arena_base) hipFree(s->arena_base);
+            if (s->arena_base) (void)hipFree(s->arena_base);
             delete s->arena;
             delete s;
             return e == hipErrorOutOfMemory ? TDCT_ENOMEM : TDCT_EDEVICE;
@@ -968,7 +968,7 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
         if (st) {
             resident_free(s);
             if (s->fake) free(s->arena_base);
-            else hipFree(s->arena_base);
+            else (void)hipFree(s->arena_base);
             delete s->arena;
             delete s;
             return st;
@@ -1128,13 +1128,13 @@ void tdct_server_destroy(tdct_server* s) {
         free(s->arena_base);
     } else {
         for (Slot& sl : s->slots) {
-            if (sl.stream) hipStreamSynchronize(sl.stream);
-            if (sl.done) hipEventDestroy(sl.done);
-            if (sl.stream) hipStreamDestroy(sl.stream);
-            if (sl.dev) hipFree(sl.dev);
-            if (sl.pinned) hipHostFree(sl.pinned);
+            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+            if (sl.dev) (void)hipFree(sl.dev);
+            if (sl.pinned) (void)hipHostFree(sl.pinned);
         }
-        if (s->arena_base) hipFree(s->arena_base);
+        if (s->arena_base) (void)hipFree(s->arena_base);
     }
     delete s->arena;
     delete s;
