@@ -19,6 +19,7 @@ The JSON line also carries:
 and, unless --no-extras:
   fused_roundtrip  encode + decode fused with no coefficients in HBM;
   per_image     the same 64-image batch with one plain launch per image;
+  forward       the int32 forward transform alone over the same batch (5 B/px);
   latency_512   one 512 x 512 image: per-call latency of each plain entry
                 point, and the PSNR of a zonal keep-10 reconstruction;
   ceiling       stream probes: the part's practical copy/read/write rates;
@@ -182,9 +183,14 @@ def latency_leg(tdct, torch, stream, side=512, reps=100):
     """One 512 x 512 image (seed 1), Q = 1: the int32 forward transform, the
     quantiser with zonal keep 10, the decoder, and the fused round trip, each
     as the median of `reps` event-timed calls; the input (256 KiB) is cache
-    resident, so these are latencies, not roofline figures. Also the host
-    clock from call to completion of one round trip, and the PSNR of the
-    keep-10 reconstruction."""
+    resident, so these are latencies, not roofline figures. The calls are
+    queued behind a spin kernel of about 20 ms, so each event pair brackets
+    device time only (with an idle queue it would also take in the host's
+    time to marshal and launch the call). The same measurement of a
+    near-empty kernel (the spin kernel for one cycle) gives the floor of the
+    method: event overhead plus one dispatch. Also the host clock from call
+    to completion of one round trip, and the PSNR of the keep-10
+    reconstruction."""
     import numpy as np
 
     import synth
@@ -197,18 +203,34 @@ def latency_leg(tdct, torch, stream, side=512, reps=100):
     rec = torch.empty_like(src)
     rt = torch.empty_like(src)
     sse = torch.zeros(1, dtype=torch.int64, device="cuda")
+    def empty():
+        with torch.cuda.stream(stream):
+            torch.cuda._sleep(1)
+
     ops = {
+        "empty_kernel": empty,
         "forward_int32": lambda: tdct.tdct_forward(src, side, side, side, Y, stream),
         "quantise_keep10": lambda: tdct.tdct_quantise(src, side, side, side, one, 10, q, stream),
         "inverse": lambda: tdct.tdct_inverse(q, one, side, side, rec, side, stream),
         "roundtrip_keep10": lambda: tdct.tdct_roundtrip(src, side, side, side, one, 10, None, rt, side,
                                                         stream),
     }
+    # Spin-kernel cycles for about 20 ms, from one timed spin.
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(1 << 20)
+        a.record(stream)
+        torch.cuda._sleep(1 << 22)
+        b.record(stream)
+    torch.cuda.synchronize()
+    hold = int((1 << 22) * 20.0 / max(a.elapsed_time(b), 1e-3))
     out = {"side": side, "reps": reps}
     for name, f in ops.items():
         f()
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        with torch.cuda.stream(stream):
+            torch.cuda._sleep(hold)
         for k in range(reps):
             ev[2 * k].record(stream)
             f()
@@ -360,6 +382,37 @@ def fused_leg(tdct, torch, W, stream, reps=10, tune=None):
     return {"kernel": "batch_kernel<32> (round trip, coefficients kept in registers)", "tune": tune,
             "ms": round(ms, 4), "gpx_s": round(px / (ms / 1e3) / 1e9, 1),
             "gbs": round(2 * px / (ms / 1e3) / 1e9, 1), "bytes_per_px": 2, "roofline": roof}
+
+
+def forward_leg(tdct, torch, W, stream, reps=10):
+    """The int32 forward transform alone (Y = T X T^t, no quantiser) of the
+    same 64 x 4096^2 batch: 1 B in + 4 B out per pixel, HBM-bound; the
+    launch shape comes from the autotuner."""
+    n = len(W["sizes"])
+    side = W["sizes"][0][0]
+    nblk = (side // 8) ** 2
+    base = W["src"].data_ptr()
+    Y = torch.empty((n, nblk, 64), dtype=torch.int32, device="cuda")
+    descs = [tdct.image_desc(tdct.OP_FORWARD, side, side, src=base + int(W["off"][i]),
+                             src_stride=side, coef=Y[i]) for i in range(n)]
+    plan = tdct.tdct_batch_plan(descs, W["qs"])
+    try:
+        tune = tdct.tdct_autotune(plan, stream, reps=2)
+        tdct.tdct_batch_run(plan, stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        for k in range(reps):
+            ev[k].record(stream)
+            tdct.tdct_batch_run(plan, stream)
+        ev[reps].record(stream)
+        torch.cuda.synchronize()
+        ms = sum(ev[k].elapsed_time(ev[k + 1]) for k in range(reps)) / reps
+    finally:
+        tdct.tdct_plan_free(plan)
+    del Y
+    gbs = 5 * W["pixels"] / (ms / 1e3) / 1e9
+    return {"kernel": "batch_kernel<16> (int32 forward)", "tune": tune, "ms": round(ms, 4),
+            "gpx_s": round(W["pixels"] / (ms / 1e3) / 1e9, 1), "gbs": round(gbs, 1),
+            "bytes_per_px": 5, "frac_of_8tbs": round(gbs / 8000.0, 4)}
 
 
 def video_leg(tdct, torch, stream, frames=256, reps=5):
@@ -718,6 +771,10 @@ def main():
     if want("per_image"):
         log("per-image launches of the same batch...")
         result["per_image"] = per_image_leg(tdct, torch, W, stream)
+    if want("forward"):
+        log("int32 forward leg...")
+        result["forward"] = forward_leg(tdct, torch, W, stream)
+        torch.cuda.empty_cache()
     del W
     torch.cuda.empty_cache()
     if want("latency_512"):

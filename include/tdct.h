@@ -206,7 +206,8 @@ typedef struct {
                               0 = one plain launch per request (comparison mode) */
     int64_t max_batch_px;  /* a batch stops growing once it holds this many pixels, so
                               small requests do not wait for a huge one (0 = no cap) */
-    tdct_tune tune;        /* launch shape of batch launches (zeros = defaults) */
+    tdct_tune tune;        /* launch shape of batch launches (zero fields: one wave per
+                              workgroup, one tile per wave) */
     int32_t fake_device_us; /* > 0: no GPU at all -- outputs live in host memory and a
                                batch "completes" this many microseconds after launch
                                (exercises admission and batching on a CPU) */

@@ -167,10 +167,17 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
         make_qconst(nullptr, 64, &qc);
         p->qcs.push_back(qc);
     }
-    // Image-uniform tiles from each image's block range.
+    // Image-uniform tiles from each image's block range; 64-block
+    // encoder-side tiles when the plan is too small to fill the device.
+    int64_t full_tiles = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t tb = tile_blocks(p->imgs[i].op);
+        full_tiles += (p->blk_off[i + 1] - p->blk_off[i] + tb - 1) / tb;
+    }
+    const bool small = shrink_tiles(full_tiles, p->num_cus);
     for (int32_t i = 0; i < n; ++i) {
         const int64_t nb = p->blk_off[i + 1] - p->blk_off[i];
-        const int tb = tile_blocks(p->imgs[i].op);
+        const int tb = small ? kDecTileBlocks : tile_blocks(p->imgs[i].op);
         for (int64_t f = 0; f < nb; f += tb) {
             Tile t;
             t.img = (uint32_t)i;

@@ -19,6 +19,15 @@ int image_flags(const ImgDesc& d);
 int fill_desc(int op, const uint8_t* src, int64_t src_stride, int32_t w, int32_t h, void* coef,
               uint8_t* dst, int64_t dst_stride, int32_t qidx, bool write_coef, ImgDesc* d);
 int launch_plain_op(int op, const ImgDesc& d, const QConst& qc, hipStream_t stream);
+// Whether a launch whose work makes `full_tiles` tiles of the ops' own size
+// (128 blocks for encoder-side ops, 64 for the decoder) should cut
+// encoder-side work into 64-block tiles instead: true while there would be
+// fewer tiles, hence waves, than the device has SIMDs (4 per CU). Each wave
+// then does half the serial work (one block per lane) and twice as many
+// SIMDs take part.
+inline bool shrink_tiles(int64_t full_tiles, int num_cus) {
+    return full_tiles < 4 * (int64_t)num_cus;
+}
 // ops: bit i set when op i occurs in the tiles (selects the kernel instance).
 int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
                  int ops, const tdct_tune& tune, int num_cus, hipStream_t stream);

@@ -15,21 +15,21 @@ namespace tdct {
 // ---- kernels -----------------------------------------------------------------
 
 // One image, quantiser constants in the kernel arguments. Wave w handles
-// tiles w, w + nwaves, ... of the image.
+// tiles w, w + nwaves, ... of the image, each of `tb` blocks (at most the
+// op's tile size).
 template <int OP>
 __global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QConst qc,
-                                                    uint32_t ntiles) {
+                                                    uint32_t ntiles, uint32_t tb) {
     extern __shared__ v4u lds[];
     v4u* wl = lds + (threadIdx.x >> 6) * (lds_wave_bytes(1 << OP) / 16);
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpg + (threadIdx.x >> 6));
     const uint32_t nwaves = gridDim.x * wpg;
     const uint32_t lane = threadIdx.x & 63;
-    constexpr uint32_t TB = OP == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
     const uint32_t nblk = (uint32_t)d.nblk;
     for (uint32_t t = wave; t < ntiles; t += nwaves) {
-        const uint32_t first = t * TB;
-        const uint32_t count = min(TB, nblk - first);
+        const uint32_t first = t * tb;
+        const uint32_t count = min(tb, nblk - first);
         run_tile<OP>(d, qc, first, count, lane, wl);
     }
 }
@@ -184,14 +184,36 @@ static int allow_lds(K kernel, uint32_t bytes) {
     return TDCT_OK;
 }
 
+// SIMDs of the current device (4 per CU), cached per thread and device.
+static uint32_t device_simds() {
+    thread_local int dev_cached = -1;
+    thread_local uint32_t simds = 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (dev != dev_cached) {
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            return 1024;
+        dev_cached = dev;
+        simds = 4u * (uint32_t)cus;
+    }
+    return simds;
+}
+
+// One wave per workgroup and one tile per wave, so that the few waves of a
+// small image spread over as many CUs as there are waves. An encoder-side
+// tile (two blocks per lane) shrinks to 64 blocks while 128-block tiles
+// would leave SIMDs without a wave: each wave then does half the serial
+// work (one block per lane) and there are twice as many of them. The int32
+// forward output (4 bytes per pixel, staged in four rounds per 128 blocks)
+// always takes 64-block tiles.
 template <int OP>
 static int launch_plain(const ImgDesc& d, const QConst& qc, hipStream_t stream) {
-    constexpr uint32_t TB = OP == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
-    const uint32_t ntiles = (uint32_t)((d.nblk + TB - 1) / TB);
-    const uint32_t wpg = 4;
-    const uint32_t grid = (ntiles + wpg - 1) / wpg;
-    const uint32_t lds = wpg * lds_wave_bytes(1 << OP);
-    hipLaunchKernelGGL(plain_kernel<OP>, dim3(grid), dim3(64 * wpg), lds, stream, d, qc, ntiles);
+    uint32_t tb = OP == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
+    if (tb > 64 && (OP == OP_FORWARD || (uint64_t)(d.nblk + tb - 1) / tb < device_simds())) tb = 64;
+    const uint32_t ntiles = (uint32_t)((d.nblk + tb - 1) / tb);
+    const uint32_t lds = lds_wave_bytes(1 << OP);
+    hipLaunchKernelGGL(plain_kernel<OP>, dim3(ntiles), dim3(64), lds, stream, d, qc, ntiles, tb);
     return check_launch("plain kernel launch");
 }
 

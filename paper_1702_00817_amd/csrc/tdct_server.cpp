@@ -337,7 +337,17 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
                 fill_desc(OP_DECODE, nullptr, 0, r.w, r.h, const_cast<void*>(in),
                           (uint8_t*)items[i].out, r.w, i, false, &imgs[i]);
             ops |= 1 << imgs[i].op;
-            const int tb = tile_blocks(imgs[i].op);
+        }
+        // 64-block encoder-side tiles when the batch is too small to fill
+        // the device.
+        int64_t full_tiles = 0;
+        for (int i = 0; i < n; ++i) {
+            const int64_t tb = tile_blocks(imgs[i].op);
+            full_tiles += (imgs[i].nblk + tb - 1) / tb;
+        }
+        const bool small = shrink_tiles(full_tiles, s->num_cus);
+        for (int i = 0; i < n; ++i) {
+            const int tb = small ? kDecTileBlocks : tile_blocks(imgs[i].op);
             for (int64_t f = 0; f < imgs[i].nblk; f += tb) {
                 Tile t;
                 t.img = (uint32_t)i;
@@ -919,8 +929,10 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
     if (!s) return TDCT_ENOMEM;
     s->cfg = *cfg;
     if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
-    if (!s->cfg.tune.waves_per_group) s->cfg.tune.waves_per_group = 4;
-    if (!s->cfg.tune.groups_per_cu) s->cfg.tune.groups_per_cu = 8;
+    // One wave per workgroup and one tile per wave: a small batch's waves
+    // land on as many CUs as there are waves.
+    if (!s->cfg.tune.waves_per_group) s->cfg.tune.waves_per_group = 1;
+    if (!s->cfg.tune.groups_per_cu) s->cfg.tune.groups_per_cu = 4096;
     if (!s->cfg.tune.tile_waves) s->cfg.tune.tile_waves = 1;
     s->fake = cfg->fake_device_us > 0;
     s->t0 = Clock::now();

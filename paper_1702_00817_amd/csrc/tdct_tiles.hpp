@@ -81,9 +81,12 @@ __device__ __forceinline__ uint32_t swz(uint32_t L) {
     return CPL == 8 ? ((L ^ (L >> 3)) & 7u) : (((L >> 1) ^ (L >> 2)) & 3u);
 }
 
-// Stores the run of 64 * CPL chunks at dst (only its first nchunks) from
-// lane-owned chunks.
-template <int CPL>
+// Stores the run of 64 * CPL chunks (only its first nchunks) from lane-owned
+// chunks: chunk m of lane L goes to dst[STRIDE * L + m]. With STRIDE = CPL
+// the run is contiguous; with STRIDE = 2 * CPL it is one half of each of 64
+// blocks of 2 * CPL chunks (an int32 block in two rounds), and every store
+// instruction still writes whole runs of CPL * 16 bytes.
+template <int CPL, int STRIDE = CPL>
 __device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint32_t nchunks,
                                           v4u* dst, uint32_t lane) {
 #pragma unroll
@@ -94,7 +97,7 @@ __device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint3
         const uint32_t c = 64u * k + lane;
         const uint32_t L = c / CPL, m = c % CPL;
         const v4u v = wl[CPL * L + (m ^ swz<CPL>(L))];
-        if (c < nchunks) st_nt4(dst + c, v);
+        if (c < nchunks) st_nt4(dst + STRIDE * L + m, v);
     }
     asm volatile("" ::: "memory");
 }
@@ -283,19 +286,22 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
 
     const uint32_t na = min(count, 64u), nb = count > 64u ? count - 64u : 0u;
     if constexpr (OP == OP_FORWARD) {
-        if (va) {
-            int32_t* oa = reinterpret_cast<int32_t*>(d.coef) + (int64_t)ba * 64;
+        // int32 Y, natural order: 16 chunks per block, staged as the first
+        // and then the second half of every block.
+        v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 16;
 #pragma unroll
-            for (int k = 0; k < 64; k += 4)
-                st_nt4(oa + k, (v4u){(uint32_t)(int)v[k].x, (uint32_t)(int)v[k + 1].x,
-                                     (uint32_t)(int)v[k + 2].x, (uint32_t)(int)v[k + 3].x});
-        }
-        if (vb) {
-            int32_t* ob = reinterpret_cast<int32_t*>(d.coef) + (int64_t)bb * 64;
+        for (int h = 0; h < 2; ++h) {
+            v4u ma[8], mb[8];
 #pragma unroll
-            for (int k = 0; k < 64; k += 4)
-                st_nt4(ob + k, (v4u){(uint32_t)(int)v[k].y, (uint32_t)(int)v[k + 1].y,
-                                     (uint32_t)(int)v[k + 2].y, (uint32_t)(int)v[k + 3].y});
+            for (int m = 0; m < 8; ++m) {
+                const int k = 32 * h + 4 * m;
+                ma[m] = (v4u){(uint32_t)(int)v[k].x, (uint32_t)(int)v[k + 1].x,
+                              (uint32_t)(int)v[k + 2].x, (uint32_t)(int)v[k + 3].x};
+                mb[m] = (v4u){(uint32_t)(int)v[k].y, (uint32_t)(int)v[k + 1].y,
+                              (uint32_t)(int)v[k + 2].y, (uint32_t)(int)v[k + 3].y};
+            }
+            stage_out<8, 16>(wl, ma, 8 * na, out + 8 * h, lane);
+            stage_out<8, 16>(wl, mb, 8 * nb, out + 1024 + 8 * h, lane);
         }
     } else if constexpr (OP == OP_ENCODE_I8ZZ) {
         // int8, zigzag order: 64 bytes (4 chunks) per block.
@@ -455,7 +461,8 @@ __device__ __forceinline__ void run_tile(const ImgDesc& d, const QC& qc, uint32_
 
 // LDS bytes one wave needs for a set of ops (bit i = op i).
 __host__ __device__ constexpr uint32_t lds_wave_bytes(int ops) {
-    return (ops & ((1 << OP_ENCODE) | (1 << OP_ROUNDTRIP) | (1 << OP_DECODE))) ? 8192u
+    return (ops & ((1 << OP_ENCODE) | (1 << OP_ROUNDTRIP) | (1 << OP_DECODE) | (1 << OP_FORWARD)))
+               ? 8192u
            : (ops & (1 << OP_ENCODE_I8ZZ)) ? 4096u
                                            : 0u;
 }
