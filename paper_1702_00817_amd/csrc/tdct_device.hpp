@@ -185,7 +185,8 @@ struct ImgDesc {
 
 // A tile is the run of blocks one wave handles in one step: up to 128
 // consecutive blocks (raster order) of one image for encoder-side ops, 64 for
-// the decoder.
+// the decoder and for the int32 forward transform (whose 4-byte output takes
+// two LDS staging rounds per 64 blocks).
 struct Tile {
     uint32_t img;
     uint32_t first_lo;  // first block index, split to keep the table 16-byte friendly
@@ -197,7 +198,7 @@ constexpr int kEncTileBlocks = 128;
 constexpr int kDecTileBlocks = 64;
 
 __host__ __device__ inline int tile_blocks(int op) {
-    return op == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
+    return (op == OP_DECODE || op == OP_FORWARD) ? kDecTileBlocks : kEncTileBlocks;
 }
 
 }  // namespace tdct

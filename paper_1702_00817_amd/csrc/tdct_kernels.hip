@@ -204,13 +204,11 @@ static uint32_t device_simds() {
 // small image spread over as many CUs as there are waves. An encoder-side
 // tile (two blocks per lane) shrinks to 64 blocks while 128-block tiles
 // would leave SIMDs without a wave: each wave then does half the serial
-// work (one block per lane) and there are twice as many of them. The int32
-// forward output (4 bytes per pixel, staged in four rounds per 128 blocks)
-// always takes 64-block tiles.
+// work (one block per lane) and there are twice as many of them.
 template <int OP>
 static int launch_plain(const ImgDesc& d, const QConst& qc, hipStream_t stream) {
-    uint32_t tb = OP == OP_DECODE ? kDecTileBlocks : kEncTileBlocks;
-    if (tb > 64 && (OP == OP_FORWARD || (uint64_t)(d.nblk + tb - 1) / tb < device_simds())) tb = 64;
+    uint32_t tb = (uint32_t)tile_blocks(OP);
+    if (tb > 64 && (uint64_t)(d.nblk + tb - 1) / tb < device_simds()) tb = 64;
     const uint32_t ntiles = (uint32_t)((d.nblk + tb - 1) / tb);
     const uint32_t lds = lds_wave_bytes(1 << OP);
     hipLaunchKernelGGL(plain_kernel<OP>, dim3(ntiles), dim3(64), lds, stream, d, qc, ntiles, tb);

@@ -92,12 +92,21 @@ __device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint3
 #pragma unroll
     for (int m = 0; m < CPL; ++m) wl[CPL * lane + ((uint32_t)m ^ swz<CPL>(lane))] = mine[m];
     lds_fence();
+    // CPL divides 64, so chunk 64 k + lane belongs to lane 64 k / CPL +
+    // lane / CPL and, for a strided run, sits at one per-lane base plus a
+    // constant per k.
+    v4u* base = dst + STRIDE * (lane / CPL) + lane % CPL;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const uint32_t c = 64u * k + lane;
         const uint32_t L = c / CPL, m = c % CPL;
         const v4u v = wl[CPL * L + (m ^ swz<CPL>(L))];
-        if (c < nchunks) st_nt4(dst + STRIDE * L + m, v);
+        if (c < nchunks) {
+            if constexpr (STRIDE == CPL)
+                st_nt4(dst + c, v);
+            else
+                st_nt4(base + (64 / CPL) * STRIDE * k, v);
+        }
     }
     asm volatile("" ::: "memory");
 }
@@ -284,6 +293,8 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
     fwd8x8(v);
     v[0] -= (s16x2){8192, 8192};
 
+    // Blocks in the a and b halves; a tile of at most 64 blocks skips the
+    // b half's staging round.
     const uint32_t na = min(count, 64u), nb = count > 64u ? count - 64u : 0u;
     if constexpr (OP == OP_FORWARD) {
         // int32 Y, natural order: 16 chunks per block, staged as the first
@@ -301,7 +312,7 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
                               (uint32_t)(int)v[k + 2].y, (uint32_t)(int)v[k + 3].y};
             }
             stage_out<8, 16>(wl, ma, 8 * na, out + 8 * h, lane);
-            stage_out<8, 16>(wl, mb, 8 * nb, out + 1024 + 8 * h, lane);
+            if (nb) stage_out<8, 16>(wl, mb, 8 * nb, out + 1024 + 8 * h, lane);
         }
     } else if constexpr (OP == OP_ENCODE_I8ZZ) {
         // int8, zigzag order: 64 bytes (4 chunks) per block.
@@ -330,7 +341,7 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
         }
         v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 4;
         stage_out<4>(wl, ma, 4 * na, out, lane);
-        stage_out<4>(wl, mb, 4 * nb, out + 256, lane);
+        if (nb) stage_out<4>(wl, mb, 4 * nb, out + 256, lane);
     } else if constexpr (OP == OP_ROUNDTRIP_NC) {
         // Encode and decode without storing coefficients. The rounding
         // float's low 24 bits are 0x400000 + q (|q| < 2^22), so one 24-bit
@@ -370,9 +381,12 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
 #pragma unroll
             for (int m = 0; m < 8; ++m) m8[m] = (v4u){qa[4 * m], qa[4 * m + 1], qa[4 * m + 2], qa[4 * m + 3]};
             stage_out<8>(wl, m8, 8 * na, out, lane);
+            if (nb) {
 #pragma unroll
-            for (int m = 0; m < 8; ++m) m8[m] = (v4u){qb[4 * m], qb[4 * m + 1], qb[4 * m + 2], qb[4 * m + 3]};
-            stage_out<8>(wl, m8, 8 * nb, out + 512, lane);
+                for (int m = 0; m < 8; ++m)
+                    m8[m] = (v4u){qb[4 * m], qb[4 * m + 1], qb[4 * m + 2], qb[4 * m + 3]};
+                stage_out<8>(wl, m8, 8 * nb, out + 512, lane);
+            }
         }
         if constexpr (OP == OP_ROUNDTRIP) {
             uint32_t px[8][2];
