@@ -194,6 +194,41 @@ def test_large_batch_64_images_4096(tdct):
         tdct.tdct_plan_free(pd)
 
 
+@pytest.mark.parametrize("tune", [dict(waves_per_group=8, groups_per_cu=4096, tile_waves=2),
+                                  dict(waves_per_group=4, groups_per_cu=4096, tile_waves=1)])
+def test_forward_int32_64_images_4096(tdct, tune):
+    """The int32 forward transform alone over the 64 images of 4096 x 4096
+    (4 GiB of coefficients), in the launch shapes the autotuner picks for
+    it; every image compared in full."""
+    import torch
+    sizes, seeds, qs = synth.large_batch_spec()
+    n, side = len(sizes), sizes[0][0]
+    buf, off, strides = synth.batch(sizes, seeds)
+    src = torch.from_numpy(buf).cuda()
+    nblk = (side // 8) ** 2
+    Y = torch.empty((n, nblk, 64), dtype=torch.int32, device="cuda")
+    base = src.data_ptr()
+    descs = [tdct.image_desc(tdct.OP_FORWARD, side, side, src=base + int(off[i]), src_stride=side,
+                             coef=Y[i]) for i in range(n)]
+    plan = tdct.tdct_batch_plan(descs, qs, tune=tune)
+    try:
+        tdct.tdct_batch_run(plan)
+        sync()
+        yh = Y.cpu().numpy()
+
+        def check(i):
+            img = synth.batch_view(buf, off, strides, sizes, i)
+            return bool(np.array_equal(yh[i], O.forward(img)))
+
+        with ThreadPoolExecutor(HOST_THREADS) as ex:
+            ok = list(ex.map(check, range(n)))
+        assert all(ok), [i for i, g in enumerate(ok) if not g]
+    finally:
+        tdct.tdct_plan_free(plan)
+        del Y
+        torch.cuda.empty_cache()
+
+
 def test_ragged_10000_images_one_persistent_launch(tdct):
     """10,000 images with log-uniform sides in [64, 2048]: full encode +
     decode round trip with coefficients, one launch from the block-offset

@@ -273,5 +273,18 @@ def test_maximum_sides(tdct, w, h):
     tdct.tdct_inverse(q, Q, w, h, rec, w)
     sync()
     _sampled_blocks_match(img, w, h, q, rec, Q, 300, w + h)
-    del img, q, rec
+    del q, rec
+    torch.cuda.empty_cache()
+    # the int32 forward transform over the same plane (up to 16 GiB of output)
+    Y = torch.empty((nblk, 64), dtype=torch.int32, device="cuda")
+    tdct.tdct_forward(img, w, w, h, Y)
+    sync()
+    nbx, nby = w // 8, h // 8
+    rng = np.random.default_rng(w + 3 * h)
+    picks = [(0, 0), (nbx - 1, nby - 1), (nbx - 1, 0), (0, nby - 1)]
+    picks += list(zip(rng.integers(0, nbx, 300).tolist(), rng.integers(0, nby, 300).tolist()))
+    for bx, by in picks:
+        blk = np.ascontiguousarray(img[8 * by:8 * by + 8, 8 * bx:8 * bx + 8].cpu().numpy())
+        assert np.array_equal(Y[by * nbx + bx].cpu().numpy(), O.forward(blk)[0]), (bx, by)
+    del img, Y
     torch.cuda.empty_cache()
