@@ -182,8 +182,9 @@ int tdct_batch_run(tdct_plan* plan, void* stream);
 int tdct_batch_graph(tdct_plan* plan, void* stream);
 
 /* Times candidate launch shapes on the plan (reps launches each, after one
- * warm-up), keeps the fastest in the plan and returns it in *best. Outputs
- * are overwritten with the same bytes by every candidate. */
+ * warm-up), then times the four fastest again in turn over max(5, reps)
+ * rounds, keeps the one with the lowest median in the plan and returns it
+ * in *best. Outputs are overwritten with the same bytes by every candidate. */
 int tdct_autotune(tdct_plan* plan, void* stream, int32_t reps, tdct_tune* best);
 
 int tdct_plan_info_get(const tdct_plan* plan, tdct_plan_info* out);

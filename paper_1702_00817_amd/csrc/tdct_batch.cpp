@@ -280,11 +280,37 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
         return TDCT_EDEVICE;
     }
     const tdct_tune saved = p->tune;
+    // One launch in shape t, timed with events on the plan's stream.
+    auto time_one = [&](const tdct_tune& t, float* ms) -> int {
+        p->tune = t;
+        hipError_t e = hipEventRecord(e0, s);
+        int st = TDCT_OK;
+        if (e == hipSuccess && (st = run(p, s))) return st;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+        if (e != hipSuccess) {
+            set_error("autotune timing", e);
+            return TDCT_EDEVICE;
+        }
+        return TDCT_OK;
+    };
+    auto median = [](std::vector<float> v) {
+        std::sort(v.begin(), v.end());
+        return v[v.size() / 2];
+    };
+    struct Cand {
+        tdct_tune t;
+        float ms;
+    };
+    std::vector<Cand> cands;
+    std::vector<std::vector<float>> finals;
+    size_t k = 0;
     tdct_tune winner = saved;
-    float best_ms = 1e30f;
     int st = TDCT_OK;
-    // Launch shapes: persistent grids of 1..16 resident waves per CU, and a
-    // full grid (every wave takes tile_waves tiles and exits).
+    // Stage 1: every launch shape (persistent grids of 1..16 resident waves
+    // per CU, and a full grid where every wave takes tile_waves tiles and
+    // exits), one warm-up and `reps` timed launches each.
     const int wpgs[] = {1, 2, 4, 8};
     const int gpcs[] = {1, 2, 4, 8, 16, 4096};
     const int tws[] = {1, 2};
@@ -297,30 +323,32 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
                 t.waves_per_group = wpg;
                 t.groups_per_cu = gpc;
                 t.tile_waves = tw;
-                p->tune = t;
-                if ((st = run(p, s))) goto done;  // warm-up
+                float m = 0;
+                if ((st = time_one(t, &m))) goto done;  // warm-up
                 std::vector<float> ms;
                 for (int r = 0; r < reps; ++r) {
-                    hipError_t e = hipEventRecord(e0, s);
-                    if (e == hipSuccess && (st = run(p, s))) goto done;
-                    if (e == hipSuccess) e = hipEventRecord(e1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float m = 0;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
-                    if (e != hipSuccess) {
-                        set_error("autotune timing", e);
-                        st = TDCT_EDEVICE;
-                        goto done;
-                    }
+                    if ((st = time_one(t, &m))) goto done;
                     ms.push_back(m);
                 }
-                std::sort(ms.begin(), ms.end());
-                const float med = ms[ms.size() / 2];
-                if (med < best_ms) {
-                    best_ms = med;
-                    winner = t;
-                }
+                cands.push_back({t, median(ms)});
             }
+    // Stage 2: the four fastest again, round-robin over several rounds, so
+    // that a drift of the clocks between candidates cannot pick the winner.
+    std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+    k = std::min<size_t>(4, cands.size());
+    finals.assign(k, {});
+    for (int r = 0; r < std::max(5, reps); ++r)
+        for (size_t c = 0; c < k; ++c) {
+            float m = 0;
+            if ((st = time_one(cands[c].t, &m))) goto done;
+            finals[c].push_back(m);
+        }
+    if (k) {
+        size_t b = 0;
+        for (size_t c = 1; c < k; ++c)
+            if (median(finals[c]) < median(finals[b])) b = c;
+        winner = cands[b].t;
+    }
 done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
