@@ -254,7 +254,9 @@ def latency_leg(tdct, torch, stream, side=512, reps=100):
 
 def batched_leg(tdct, torch, stream, n=10000, reps=5):
     """10,000 ragged images, encode + decode round trip with coefficients:
-    persistent launch (graph replay) vs one plain launch per image."""
+    persistent launch (graph replay) vs one plain launch per image, and vs
+    the same per-image launches captured in one hipGraph (no launch
+    overhead: what remains is the cost of 10,000 small grids)."""
     import numpy as np
 
     import synth
@@ -290,12 +292,32 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
         torch.cuda.synchronize()
         per_s = (time.perf_counter() - t0) / reps
         info = tdct.tdct_plan_info_get(plan)
+        # the per-image launches captured once and replayed
+        want = dst.clone()
+        dst.zero_()
+        torch.cuda.synchronize()
+        cap = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cap):
+            tdct.tdct_run_per_image(descs, qs, cap)
+        g.replay()
+        torch.cuda.synchronize()
+        graph_same = bool(torch.equal(dst, want))
+        del want
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        per_graph_s = (time.perf_counter() - t0) / reps
+        del g
     finally:
         tdct.tdct_plan_free(plan)
     del src, coef, dst
     return {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
             "graph_gpx_s": round(px / graph_s / 1e9, 2), "graph_ms": round(graph_s * 1e3, 3),
             "per_image_gpx_s": round(px / per_s / 1e9, 2), "per_image_ms": round(per_s * 1e3, 3),
+            "per_image_graph_gpx_s": round(px / per_graph_s / 1e9, 2),
+            "per_image_graph_ms": round(per_graph_s * 1e3, 3), "per_image_graph_same": graph_same,
             "speedup": round(per_s / graph_s, 2), "bytes_per_px": 4}
 
 
