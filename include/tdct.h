@@ -147,10 +147,13 @@ typedef struct {
     int64_t dst_stride;
 } tdct_image_desc;
 
-/* Launch shape of the persistent kernel. Zero fields take defaults. */
+/* Launch shape of the persistent kernel. Zero fields take the defaults:
+ * one wave per workgroup, a full grid (groups_per_cu 4096: the grid is
+ * capped at one wave per tile step) and one tile per step. */
 typedef struct {
     int32_t waves_per_group; /* 1, 2, 4 or 8 (64-lane waves per workgroup) */
-    int32_t groups_per_cu;   /* resident workgroups per compute unit; grid = CUs * this */
+    int32_t groups_per_cu;   /* workgroups per compute unit; grid = CUs * this, capped at the
+                                workgroups needed for one tile step per wave */
     int32_t tile_waves;      /* consecutive wave-tiles one wave takes per step (1, 2, 4) */
     int32_t reserved;
 } tdct_tune;

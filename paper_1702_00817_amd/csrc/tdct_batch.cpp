@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <new>
 #include <utility>
 #include <vector>
@@ -44,10 +45,13 @@ struct tdct_plan {
 
 namespace {
 
+// One wave per workgroup and one tile per wave over a full grid: a small
+// plan's waves land on as many CUs as there are waves, and on large plans
+// the autotuner's pick is a full grid too.
 tdct_tune default_tune() {
     tdct_tune t{};
-    t.waves_per_group = 4;
-    t.groups_per_cu = 8;
+    t.waves_per_group = 1;
+    t.groups_per_cu = 4096;
     t.tile_waves = 1;
     return t;
 }
@@ -114,112 +118,114 @@ extern "C" {
 
 int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs, int32_t nq,
                     const tdct_tune* tune_or_null, tdct_plan** out) {
-    if (!out || n < 0 || (n > 0 && !imgs) || nq < 0 || (nq > 0 && !qtabs)) return TDCT_EINVAL;
-    *out = nullptr;
-    tdct_tune tune;
-    int st = normalise_tune(tune_or_null, &tune);
-    if (st) return st;
-    for (int32_t k = 0; k < nq; ++k)
-        if ((st = validate_q(&qtabs[k]))) return st;
-    for (int32_t i = 0; i < n; ++i)
-        if ((st = validate_image(imgs[i], nq))) return st;
+    return abi_call([&]() -> int {
+        if (!out || n < 0 || (n > 0 && !imgs) || nq < 0 || (nq > 0 && !qtabs)) return TDCT_EINVAL;
+        *out = nullptr;
+        tdct_tune tune;
+        int st = normalise_tune(tune_or_null, &tune);
+        if (st) return st;
+        for (int32_t k = 0; k < nq; ++k)
+            if ((st = validate_q(&qtabs[k]))) return st;
+        for (int32_t i = 0; i < n; ++i)
+            if ((st = validate_image(imgs[i], nq))) return st;
 
-    tdct_plan* p = new (std::nothrow) tdct_plan();
-    if (!p) return TDCT_ENOMEM;
-    p->tune = tune;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) {
-        set_error("device query", e);
-        delete p;
-        return TDCT_EDEVICE;
-    }
+        // freed with everything it holds on any early return
+        std::unique_ptr<tdct_plan, void (*)(tdct_plan*)> p(new (std::nothrow) tdct_plan(),
+                                                           tdct_plan_free);
+        if (!p) return TDCT_ENOMEM;
+        p->tune = tune;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) {
+            set_error("device query", e);
+            return TDCT_EDEVICE;
+        }
 
-    // Quantiser constants per distinct (table, keep) pair.
-    std::map<std::pair<int, int>, int> qindex;
-    p->imgs.resize(n);
-    p->blk_off.assign((size_t)n + 1, 0);
-    for (int32_t i = 0; i < n; ++i) {
-        const tdct_image_desc& im = imgs[i];
-        const int keep = (im.op == TDCT_OP_ENCODE || im.op == TDCT_OP_ROUNDTRIP) ? im.keep : 64;
-        const int qt = im.op == TDCT_OP_FORWARD ? -1 : im.qtab;
-        auto key = std::make_pair(qt, keep);
-        auto it = qindex.find(key);
-        int qi;
-        if (it == qindex.end()) {
-            qi = (int)p->qcs.size();
+        // Quantiser constants per distinct (table, keep) pair.
+        std::map<std::pair<int, int>, int> qindex;
+        p->imgs.resize(n);
+        p->blk_off.assign((size_t)n + 1, 0);
+        for (int32_t i = 0; i < n; ++i) {
+            const tdct_image_desc& im = imgs[i];
+            const int keep = (im.op == TDCT_OP_ENCODE || im.op == TDCT_OP_ROUNDTRIP) ? im.keep : 64;
+            const int qt = im.op == TDCT_OP_FORWARD ? -1 : im.qtab;
+            auto key = std::make_pair(qt, keep);
+            auto it = qindex.find(key);
+            int qi;
+            if (it == qindex.end()) {
+                qi = (int)p->qcs.size();
+                QConst qc;
+                make_qconst(qt >= 0 ? &qtabs[qt] : nullptr, keep, &qc);
+                p->qcs.push_back(qc);
+                qindex.emplace(key, qi);
+            } else {
+                qi = it->second;
+            }
+            fill_desc(im.op, im.src, im.src_stride, im.w, im.h, im.coef, im.dst, im.dst_stride, qi,
+                      im.op == TDCT_OP_ROUNDTRIP && im.coef != nullptr, &p->imgs[i]);
+            p->blk_off[i + 1] = p->blk_off[i] + p->imgs[i].nblk;
+            p->ops |= 1 << p->imgs[i].op;
+            p->pixels += (int64_t)im.w * im.h;
+        }
+        if (p->qcs.empty()) {
             QConst qc;
-            make_qconst(qt >= 0 ? &qtabs[qt] : nullptr, keep, &qc);
+            make_qconst(nullptr, 64, &qc);
             p->qcs.push_back(qc);
-            qindex.emplace(key, qi);
-        } else {
-            qi = it->second;
         }
-        fill_desc(im.op, im.src, im.src_stride, im.w, im.h, im.coef, im.dst, im.dst_stride, qi,
-                  im.op == TDCT_OP_ROUNDTRIP && im.coef != nullptr, &p->imgs[i]);
-        p->blk_off[i + 1] = p->blk_off[i] + p->imgs[i].nblk;
-        p->ops |= 1 << p->imgs[i].op;
-        p->pixels += (int64_t)im.w * im.h;
-    }
-    if (p->qcs.empty()) {
-        QConst qc;
-        make_qconst(nullptr, 64, &qc);
-        p->qcs.push_back(qc);
-    }
-    // Image-uniform tiles from each image's block range; 64-block
-    // encoder-side tiles when the plan is too small to fill the device.
-    int64_t full_tiles = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        const int64_t tb = tile_blocks(p->imgs[i].op);
-        full_tiles += (p->blk_off[i + 1] - p->blk_off[i] + tb - 1) / tb;
-    }
-    const bool small = shrink_tiles(full_tiles, p->num_cus);
-    for (int32_t i = 0; i < n; ++i) {
-        const int64_t nb = p->blk_off[i + 1] - p->blk_off[i];
-        const int tb = small ? kDecTileBlocks : tile_blocks(p->imgs[i].op);
-        for (int64_t f = 0; f < nb; f += tb) {
-            Tile t;
-            t.img = (uint32_t)i;
-            t.first_lo = (uint32_t)f;
-            t.first_hi = (uint32_t)(f >> 32);
-            t.count = (uint32_t)std::min<int64_t>(tb, nb - f);
-            p->tiles.push_back(t);
+        // Image-uniform tiles from each image's block range; 64-block
+        // encoder-side tiles when the plan is too small to fill the device.
+        int64_t full_tiles = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t tb = tile_blocks(p->imgs[i].op);
+            full_tiles += (p->blk_off[i + 1] - p->blk_off[i] + tb - 1) / tb;
         }
-    }
-    if (p->tiles.size() >= 0xffffffffull) {
-        delete p;
-        return TDCT_EINVAL;
-    }
-    // One device allocation: tiles | descriptors | constants (256-B aligned parts).
-    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t tb = up(p->tiles.size() * sizeof(Tile) + 16);
-    const size_t ib = up(p->imgs.size() * sizeof(ImgDesc) + 16);
-    const size_t qb = up(p->qcs.size() * sizeof(QConst));
-    p->dev_bytes = tb + ib + qb;
-    e = hipMalloc(&p->dev, p->dev_bytes);
-    if (e != hipSuccess) {
-        set_error("plan tables", e);
-        delete p;
-        return TDCT_ENOMEM;
-    }
-    char* base = (char*)p->dev;
-    p->tiles_d = (Tile*)base;
-    p->imgs_d = (ImgDesc*)(base + tb);
-    p->qcs_d = (QConst*)(base + tb + ib);
-    e = hipMemcpy(p->tiles_d, p->tiles.data(), p->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(p->imgs_d, p->imgs.data(), p->imgs.size() * sizeof(ImgDesc), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(p->qcs_d, p->qcs.data(), p->qcs.size() * sizeof(QConst), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        set_error("plan upload", e);
-        (void)hipFree(p->dev);
-        delete p;
-        return TDCT_EDEVICE;
-    }
-    *out = p;
-    return TDCT_OK;
+        const bool small = shrink_tiles(full_tiles, p->num_cus);
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t nb = p->blk_off[i + 1] - p->blk_off[i];
+            const int tb = small ? kDecTileBlocks : tile_blocks(p->imgs[i].op);
+            for (int64_t f = 0; f < nb; f += tb) {
+                Tile t;
+                t.img = (uint32_t)i;
+                t.first_lo = (uint32_t)f;
+                t.first_hi = (uint32_t)(f >> 32);
+                t.count = (uint32_t)std::min<int64_t>(tb, nb - f);
+                p->tiles.push_back(t);
+            }
+        }
+        if (p->tiles.size() >= 0xffffffffull) return TDCT_EINVAL;
+        // One device allocation: tiles | descriptors | constants (256-B aligned parts).
+        auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+        const size_t tb = up(p->tiles.size() * sizeof(Tile) + 16);
+        const size_t ib = up(p->imgs.size() * sizeof(ImgDesc) + 16);
+        const size_t qb = up(p->qcs.size() * sizeof(QConst));
+        p->dev_bytes = tb + ib + qb;
+        e = hipMalloc(&p->dev, p->dev_bytes);
+        if (e != hipSuccess) {
+            p->dev = nullptr;
+            set_error("plan tables", e);
+            return TDCT_ENOMEM;
+        }
+        char* base = (char*)p->dev;
+        p->tiles_d = (Tile*)base;
+        p->imgs_d = (ImgDesc*)(base + tb);
+        p->qcs_d = (QConst*)(base + tb + ib);
+        e = hipMemcpy(p->tiles_d, p->tiles.data(), p->tiles.size() * sizeof(Tile),
+                      hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->imgs_d, p->imgs.data(), p->imgs.size() * sizeof(ImgDesc),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->qcs_d, p->qcs.data(), p->qcs.size() * sizeof(QConst),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            set_error("plan upload", e);
+            return TDCT_EDEVICE;
+        }
+        *out = p.release();
+        return TDCT_OK;
+    });
 }
 
 int tdct_batch_run(tdct_plan* p, void* stream) {
@@ -271,95 +277,99 @@ int tdct_batch_graph(tdct_plan* p, void* stream) {
 }
 
 int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
-    if (!p || reps < 1) return TDCT_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return TDCT_EDEVICE;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return TDCT_EDEVICE;
-    }
-    const tdct_tune saved = p->tune;
-    // One launch in shape t, timed with events on the plan's stream.
-    auto time_one = [&](const tdct_tune& t, float* ms) -> int {
-        p->tune = t;
-        hipError_t e = hipEventRecord(e0, s);
-        int st = TDCT_OK;
-        if (e == hipSuccess && (st = run(p, s))) return st;
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
-        if (e != hipSuccess) {
-            set_error("autotune timing", e);
+    return abi_call([&]() -> int {
+        if (!p || reps < 1) return TDCT_EINVAL;
+        hipStream_t s = (hipStream_t)stream;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return TDCT_EDEVICE;
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
             return TDCT_EDEVICE;
         }
-        return TDCT_OK;
-    };
-    auto median = [](std::vector<float> v) {
-        std::sort(v.begin(), v.end());
-        return v[v.size() / 2];
-    };
-    struct Cand {
-        tdct_tune t;
-        float ms;
-    };
-    std::vector<Cand> cands;
-    std::vector<std::vector<float>> finals;
-    size_t k = 0;
-    tdct_tune winner = saved;
-    int st = TDCT_OK;
-    // Stage 1: every launch shape (persistent grids of 1..16 resident waves
-    // per CU, and a full grid where every wave takes tile_waves tiles and
-    // exits), one warm-up and `reps` timed launches each.
-    const int wpgs[] = {1, 2, 4, 8};
-    const int gpcs[] = {1, 2, 4, 8, 16, 4096};
-    const int tws[] = {1, 2};
-    for (int wpg : wpgs)
-        for (int gpc : gpcs)
-            for (int tw : tws) {
-                if (gpc < 4096 && wpg * gpc > 32) continue;  // at most 32 waves per CU are resident
-                if (batch_lds_bytes(p->ops, wpg) > 160 * 1024) continue;
-                tdct_tune t{};
-                t.waves_per_group = wpg;
-                t.groups_per_cu = gpc;
-                t.tile_waves = tw;
-                float m = 0;
-                if ((st = time_one(t, &m))) goto done;  // warm-up
-                std::vector<float> ms;
-                for (int r = 0; r < reps; ++r) {
-                    if ((st = time_one(t, &m))) goto done;
-                    ms.push_back(m);
-                }
-                cands.push_back({t, median(ms)});
+        const tdct_tune saved = p->tune;
+        // One launch in shape t, timed with events on the plan's stream.
+        auto time_one = [&](const tdct_tune& t, float* ms) -> int {
+            p->tune = t;
+            hipError_t e = hipEventRecord(e0, s);
+            int st = TDCT_OK;
+            if (e == hipSuccess && (st = run(p, s))) return st;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+            if (e != hipSuccess) {
+                set_error("autotune timing", e);
+                return TDCT_EDEVICE;
             }
-    // Stage 2: the four fastest again, round-robin over several rounds, so
-    // that a drift of the clocks between candidates cannot pick the winner.
-    std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
-    k = std::min<size_t>(4, cands.size());
-    finals.assign(k, {});
-    for (int r = 0; r < std::max(5, reps); ++r)
-        for (size_t c = 0; c < k; ++c) {
-            float m = 0;
-            if ((st = time_one(cands[c].t, &m))) goto done;
-            finals[c].push_back(m);
+            return TDCT_OK;
+        };
+        auto median = [](std::vector<float> v) {
+            std::sort(v.begin(), v.end());
+            return v[v.size() / 2];
+        };
+        struct Cand {
+            tdct_tune t;
+            float ms;
+        };
+        std::vector<Cand> cands;
+        std::vector<std::vector<float>> finals;
+        size_t k = 0;
+        tdct_tune winner = saved;
+        int st = TDCT_OK;
+        // Stage 1: every launch shape (persistent grids of 1..16 resident waves
+        // per CU, and a full grid where every wave takes tile_waves tiles and
+        // exits), one warm-up and `reps` timed launches each.
+        const int wpgs[] = {1, 2, 4, 8};
+        const int gpcs[] = {1, 2, 4, 8, 16, 4096};
+        const int tws[] = {1, 2};
+        for (int wpg : wpgs)
+            for (int gpc : gpcs)
+                for (int tw : tws) {
+                    // at most 32 waves per CU are resident
+                    if (gpc < 4096 && wpg * gpc > 32) continue;
+                    if (batch_lds_bytes(p->ops, wpg) > 160 * 1024) continue;
+                    tdct_tune t{};
+                    t.waves_per_group = wpg;
+                    t.groups_per_cu = gpc;
+                    t.tile_waves = tw;
+                    float m = 0;
+                    if ((st = time_one(t, &m))) goto done;  // warm-up
+                    std::vector<float> ms;
+                    for (int r = 0; r < reps; ++r) {
+                        if ((st = time_one(t, &m))) goto done;
+                        ms.push_back(m);
+                    }
+                    cands.push_back({t, median(ms)});
+                }
+        // Stage 2: the four fastest again, round-robin over several rounds, so
+        // that a drift of the clocks between candidates cannot pick the winner.
+        std::sort(cands.begin(), cands.end(),
+                  [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+        k = std::min<size_t>(4, cands.size());
+        finals.assign(k, {});
+        for (int r = 0; r < std::max(5, reps); ++r)
+            for (size_t c = 0; c < k; ++c) {
+                float m = 0;
+                if ((st = time_one(cands[c].t, &m))) goto done;
+                finals[c].push_back(m);
+            }
+        if (k) {
+            size_t b = 0;
+            for (size_t c = 1; c < k; ++c)
+                if (median(finals[c]) < median(finals[b])) b = c;
+            winner = cands[b].t;
         }
-    if (k) {
-        size_t b = 0;
-        for (size_t c = 1; c < k; ++c)
-            if (median(finals[c]) < median(finals[b])) b = c;
-        winner = cands[b].t;
-    }
-done:
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st) {
-        p->tune = saved;
-        return st;
-    }
-    free_graph(p);  // a captured graph holds the launch shape it was made with
-    p->tune = winner;
-    if (best) *best = winner;
-    return TDCT_OK;
+    done:
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st) {
+            p->tune = saved;
+            return st;
+        }
+        free_graph(p);  // a captured graph holds the launch shape it was made with
+        p->tune = winner;
+        if (best) *best = winner;
+        return TDCT_OK;
+    });
 }
 
 int tdct_plan_info_get(const tdct_plan* p, tdct_plan_info* out) {

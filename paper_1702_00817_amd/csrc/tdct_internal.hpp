@@ -5,12 +5,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
+
 #include "tdct.h"
 #include "tdct_device.hpp"
 
 namespace tdct {
 
 void set_error(const char* what, hipError_t e);
+void set_error_text(const char* what);
+
+// Runs the body of a C-ABI call: a host allocation failure (or any other C++
+// exception) becomes a status code, so no exception crosses the ABI.
+template <class F>
+int abi_call(F&& body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        set_error_text("host memory allocation failed");
+        return TDCT_ENOMEM;
+    } catch (...) {
+        set_error_text("unexpected host error");
+        return TDCT_EDEVICE;
+    }
+}
 int check_launch(const char* what);
 int validate_plane(const void* p, int64_t stride, int32_t w, int32_t h);
 int validate_q(const tdct_qtable* Q);

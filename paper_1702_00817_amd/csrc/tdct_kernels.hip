@@ -121,6 +121,8 @@ void set_error(const char* what, hipError_t e) {
     snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
 }
 
+void set_error_text(const char* what) { snprintf(g_err, sizeof(g_err), "%s", what); }
+
 int check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -166,14 +168,14 @@ int image_flags(const ImgDesc& d) {
 template <typename K>
 static int allow_lds(K kernel, uint32_t bytes) {
     if (bytes <= 65536) return TDCT_OK;
-    static int device_max = 0;
-    if (!device_max) {
-        int dev = 0;
+    // initialised once, thread-safely, by the first caller
+    static const int device_max = [] {
+        int dev = 0, m = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&device_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-                hipSuccess)
-            device_max = 65536;
-    }
+            hipDeviceGetAttribute(&m, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return 65536;
+        return m;
+    }();
     if ((int)bytes > device_max) return TDCT_EINVAL;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

@@ -32,6 +32,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -486,7 +487,13 @@ double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
             sl.fake_fail = s->cfg.fake_fail_every > 0 && (s->batches % s->cfg.fake_fail_every) == 0;
         }
         lk.unlock();
-        const int st = launch_batch_on_slot(s, sl, items);
+        int st;
+        try {
+            st = launch_batch_on_slot(s, sl, items);
+        } catch (const std::bad_alloc&) {  // the batch fails, the server carries on
+            set_error_text("host memory allocation for a batch failed");
+            st = TDCT_ENOMEM;
+        }
         lk.lock();
         if (st) {
             memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
@@ -920,75 +927,64 @@ void scheduler(tdct_server* s) {
 extern "C" {
 
 int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
-    if (!cfg || !out) return TDCT_EINVAL;
-    *out = nullptr;
-    if (cfg->budget_bytes <= 0 || cfg->streams < 1 || cfg->streams > 16 || cfg->max_batch < 0 ||
-        cfg->max_wait_us < 0 || cfg->max_batch_px < 0)
-        return TDCT_EINVAL;
-    tdct_server* s = new (std::nothrow) tdct_server();
-    if (!s) return TDCT_ENOMEM;
-    s->cfg = *cfg;
-    if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
-    // One wave per workgroup and one tile per wave: a small batch's waves
-    // land on as many CUs as there are waves.
-    if (!s->cfg.tune.waves_per_group) s->cfg.tune.waves_per_group = 1;
-    if (!s->cfg.tune.groups_per_cu) s->cfg.tune.groups_per_cu = 4096;
-    if (!s->cfg.tune.tile_waves) s->cfg.tune.tile_waves = 1;
-    s->fake = cfg->fake_device_us > 0;
-    s->t0 = Clock::now();
-    s->arena = new Arena(cfg->budget_bytes);
-    s->slots.resize(cfg->resident ? 0 : (size_t)cfg->streams);
-    if (s->fake) {
-        s->arena_base = (char*)malloc((size_t)cfg->budget_bytes);
-        if (!s->arena_base) {
-            delete s->arena;
-            delete s;
-            return TDCT_ENOMEM;
-        }
-    } else {
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess)
-            e = hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipMalloc((void**)&s->arena_base, (size_t)cfg->budget_bytes);
-        // Each slot starts with table buffers for ~16k tiles, so the serving
-        // loop itself allocates only for unusually large batches.
-        const size_t table0 = 256 * 1024;
-        for (Slot& sl : s->slots) {
-            if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-            if (e == hipSuccess && (e = hipMalloc(&sl.dev, table0)) == hipSuccess) sl.dev_cap = table0;
-            if (e == hipSuccess && (e = hipHostMalloc(&sl.pinned, table0, hipHostMallocDefault)) == hipSuccess)
-                sl.pinned_cap = table0;
-        }
-        if (e != hipSuccess) {
-            set_error("server create", e);
+    return abi_call([&]() -> int {
+        if (!cfg || !out) return TDCT_EINVAL;
+        *out = nullptr;
+        if (cfg->budget_bytes <= 0 || cfg->streams < 1 || cfg->streams > 16 || cfg->max_batch < 0 ||
+            cfg->max_wait_us < 0 || cfg->max_batch_px < 0)
+            return TDCT_EINVAL;
+        // On any early return the partly built server goes through
+        // tdct_server_destroy, which frees whatever it holds.
+        std::unique_ptr<tdct_server, void (*)(tdct_server*)> s(new (std::nothrow) tdct_server(),
+                                                               tdct_server_destroy);
+        if (!s) return TDCT_ENOMEM;
+        s->cfg = *cfg;
+        if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
+        // The batch form's default shape: one wave per workgroup and one tile
+        // per wave, so a small batch's waves land on as many CUs as there are.
+        if (!s->cfg.tune.waves_per_group) s->cfg.tune.waves_per_group = 1;
+        if (!s->cfg.tune.groups_per_cu) s->cfg.tune.groups_per_cu = 4096;
+        if (!s->cfg.tune.tile_waves) s->cfg.tune.tile_waves = 1;
+        s->fake = cfg->fake_device_us > 0;
+        s->t0 = Clock::now();
+        s->arena = new Arena(cfg->budget_bytes);
+        s->slots.resize(cfg->resident ? 0 : (size_t)cfg->streams);
+        if (s->fake) {
+            s->arena_base = (char*)malloc((size_t)cfg->budget_bytes);
+            if (!s->arena_base) return TDCT_ENOMEM;
+        } else {
+            int dev = 0;
+            hipError_t e = hipGetDevice(&dev);
+            if (e == hipSuccess)
+                e = hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e == hipSuccess &&
+                (e = hipMalloc((void**)&s->arena_base, (size_t)cfg->budget_bytes)) != hipSuccess)
+                s->arena_base = nullptr;
+            // Each slot starts with table buffers for ~16k tiles, so the serving
+            // loop itself allocates only for unusually large batches.
+            const size_t table0 = 256 * 1024;
             for (Slot& sl : s->slots) {
-                if (sl.done) (void)hipEventDestroy(sl.done);
-                if (sl.stream) (void)hipStreamDestroy(sl.stream);
-                if (sl.dev) (void)hipFree(sl.dev);
-                if (sl.pinned) (void)hipHostFree(sl.pinned);
+                if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+                if (e == hipSuccess && (e = hipMalloc(&sl.dev, table0)) == hipSuccess)
+                    sl.dev_cap = table0;
+                if (e == hipSuccess &&
+                    (e = hipHostMalloc(&sl.pinned, table0, hipHostMallocDefault)) == hipSuccess)
+                    sl.pinned_cap = table0;
             }
-            if (s->arena_base) (void)hipFree(s->arena_base);
-            delete s->arena;
-            delete s;
-            return e == hipErrorOutOfMemory ? TDCT_ENOMEM : TDCT_EDEVICE;
+            if (e != hipSuccess) {
+                set_error("server create", e);
+                return e == hipErrorOutOfMemory ? TDCT_ENOMEM : TDCT_EDEVICE;
+            }
         }
-    }
-    if (s->cfg.resident) {
-        const int st = resident_init(s);
-        if (st) {
-            resident_free(s);
-            if (s->fake) free(s->arena_base);
-            else (void)hipFree(s->arena_base);
-            delete s->arena;
-            delete s;
-            return st;
+        if (s->cfg.resident) {
+            const int st = resident_init(s.get());
+            if (st) return st;
         }
-    }
-    s->worker = std::thread(scheduler, s);
-    *out = s;
-    return TDCT_OK;
+        s->worker = std::thread(scheduler, s.get());
+        *out = s.release();
+        return TDCT_OK;
+    });
 }
 
 static int submit_locked(tdct_server* s, const tdct_request* req, bool release_on_done,
@@ -1035,10 +1031,12 @@ static int submit_now(tdct_server* s, const tdct_request* req, bool release_on_d
 }
 
 int tdct_server_submit(tdct_server* s, const tdct_request* req, uint64_t* ticket) {
-    if (!s || !req || !ticket) return TDCT_EINVAL;
-    const int st = validate_for(s, *req);
-    if (st) return st;
-    return submit_now(s, req, false, ticket);
+    return abi_call([&]() -> int {
+        if (!s || !req || !ticket) return TDCT_EINVAL;
+        const int st = validate_for(s, *req);
+        if (st) return st;
+        return submit_now(s, req, false, ticket);
+    });
 }
 
 static void fill_result(const tdct_server* s, const Req& q, tdct_result* out) {
@@ -1096,7 +1094,7 @@ int tdct_server_drain(tdct_server* s) {
     return TDCT_OK;
 }
 
-int tdct_server_stats(tdct_server* s, tdct_stats* out) {
+static int server_stats(tdct_server* s, tdct_stats* out) {
     if (!s || !out) return TDCT_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->st;
@@ -1119,6 +1117,10 @@ int tdct_server_stats(tdct_server* s, tdct_stats* out) {
         out->mean_us = sum / (double)v.size();
     }
     return TDCT_OK;
+}
+
+int tdct_server_stats(tdct_server* s, tdct_stats* out) {
+    return abi_call([&]() -> int { return server_stats(s, out); });
 }
 
 const char* tdct_server_last_error(tdct_server* s) {
@@ -1152,9 +1154,9 @@ void tdct_server_destroy(tdct_server* s) {
     delete s;
 }
 
-int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us, int32_t n,
-                       int32_t keep_outputs, uint64_t* tickets_out, double* latency_us,
-                       int32_t* status) {
+static int server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us,
+                         int32_t n, int32_t keep_outputs, uint64_t* tickets_out,
+                         double* latency_us, int32_t* status) {
     if (!s || n < 0 || (n > 0 && (!reqs || !arrival_us))) return TDCT_EINVAL;
     int64_t kept = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -1191,6 +1193,14 @@ int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* a
         if (ok && !keep_outputs) s->reqs.erase(it);
     }
     return TDCT_OK;
+}
+
+int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us, int32_t n,
+                       int32_t keep_outputs, uint64_t* tickets_out, double* latency_us,
+                       int32_t* status) {
+    return abi_call([&]() -> int {
+        return server_replay(s, reqs, arrival_us, n, keep_outputs, tickets_out, latency_us, status);
+    });
 }
 
 }  // extern "C"

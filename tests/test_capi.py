@@ -174,6 +174,22 @@ def test_fake_server_replay_and_shutdown_with_work_in_flight(tdct):
         tdct.tdct_server_destroy(s)  # drains the ten in flight, then stops
 
 
+def test_failed_server_create_frees_what_it_built(tdct):
+    """A fake-device server whose arena cannot be allocated (4 EiB) fails
+    with TDCT_ENOMEM, in stream and in resident mode; its partly built state
+    goes through the destroy path, and a server created afterwards works."""
+    for resident in (0, 1):
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_create(tdct.server_cfg(1 << 62, fake_device_us=10, resident=resident))
+        assert e.value.status == tdct.TDCT_ENOMEM
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 20, fake_device_us=10))
+    try:
+        t = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 64, 64))
+        assert tdct.tdct_server_wait(s, t).status == tdct.TDCT_OK
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
 def test_server_rejects_bad_requests(tdct):
     s = tdct.tdct_server_create(tdct.server_cfg(1 << 20, fake_device_us=10))
     try:
