@@ -54,7 +54,7 @@ __global__ __launch_bounds__(512) void batch_kernel(const Tile* __restrict__ til
         const uint32_t tend = min(t0 + tile_waves, ntiles);
         for (uint32_t t = t0; t < tend; ++t) {
             const Tile tl = tiles[t];
-            const ImgDesc& d = imgs[tl.img];
+            const ImgDesc d = global_desc(imgs[tl.img]);
             const QConst& qc = qcs[d.qidx];
             const int op = (OPS & (OPS - 1)) == 0 ? __builtin_ctz(OPS) : d.op;
             switch (op) {

@@ -129,14 +129,6 @@ __device__ void front_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0) {
     __hip_atomic_store(&a.st->stop_epoch, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The job's pointers came through LDS; rebuilding them as global-space
-// pointers lets the tile code use global instead of flat instructions.
-template <class T>
-__device__ __forceinline__ T* global_ptr(T* p) {
-    typedef __attribute__((address_space(1))) T GT;
-    return (T*)(GT*)(uintptr_t)p;
-}
-
 // Codes tiles [tile0, tile1) of one image. A lone worker wave is bound by
 // memory latency, so while it codes a tile it already loads the next one's
 // inputs (the tile code calls the hook once the current inputs are
@@ -258,10 +250,8 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
                    (a.ring_jobs - 1);
             jl[k] = reinterpret_cast<const v4u*>(a.jobs + slot)[k];
             lds_fence();
-            d = uniform_copy(&J->d);
-            d.src = global_ptr(d.src);
-            d.dst = global_ptr(d.dst);
-            d.coef = global_ptr(d.coef);
+            // the job's pointers came through LDS
+            d = global_desc(uniform_copy(&J->d));
             cur_base = first_lane64(J->base);
             ntiles = __builtin_amdgcn_readfirstlane(J->ntiles);
             done_value = __builtin_amdgcn_readfirstlane(J->done_value);

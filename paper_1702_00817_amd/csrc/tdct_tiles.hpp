@@ -48,6 +48,25 @@ __device__ __forceinline__ void st_nt2(void* p, v2u v) {
     __builtin_nontemporal_store(v, reinterpret_cast<v2u*>(p));
 }
 
+// A pointer the compiler cannot place in an address space (read from a
+// table in memory or from LDS) is generic, and generic accesses become FLAT
+// instructions, which also count against the LDS counter: every LDS fence of
+// the tile code would then wait for the wave's outstanding global stores.
+// Rebuilding it as a global-space pointer gives global instructions.
+template <class T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+    typedef __attribute__((address_space(1))) T GT;
+    return (T*)(GT*)(uintptr_t)p;
+}
+
+// An image descriptor whose plane and coefficient pointers are global-space.
+__device__ __forceinline__ ImgDesc global_desc(ImgDesc d) {
+    d.src = global_ptr(d.src);
+    d.dst = global_ptr(d.dst);
+    d.coef = global_ptr(d.coef);
+    return d;
+}
+
 // LDS writes of this wave complete before its following LDS reads (and the
 // compiler keeps LDS accesses on their side of this point).
 __device__ __forceinline__ void lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
