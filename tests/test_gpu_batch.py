@@ -108,6 +108,47 @@ def test_ragged_mixed_batch_one_launch(tdct):
         tdct.tdct_plan_free(plan)
 
 
+def test_tile_size_and_default_shape_of_plans(tdct):
+    """Tiles are 128 blocks for encoder-side ops and 64 for the decoder and
+    the int32 forward, except that a plan whose 128-block tiles would number
+    fewer than the device's SIMDs cuts encoder-side work into 64-block
+    tiles; the default launch shape is one wave per workgroup over a full
+    grid. (Descriptors only: nothing is launched.)"""
+    import torch
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    fake = 0x100000
+    q = [np.ones(64, np.uint16)]
+
+    def tiles(descs):
+        plan = tdct.tdct_batch_plan(descs, q)
+        try:
+            info = tdct.tdct_plan_info_get(plan)
+        finally:
+            tdct.tdct_plan_free(plan)
+        assert info["tune"] == {"waves_per_group": 1, "groups_per_cu": 4096, "tile_waves": 1}
+        return info["tiles"]
+
+    def enc(side):
+        return tdct.image_desc(tdct.OP_ENCODE, side, side, src=fake, src_stride=side, coef=fake)
+
+    def dec(side):
+        return tdct.image_desc(tdct.OP_DECODE, side, side, coef=fake, dst=fake, dst_stride=side)
+
+    def fwd(side):
+        return tdct.image_desc(tdct.OP_FORWARD, side, side, src=fake, src_stride=side, coef=fake)
+
+    small = (512 // 8) ** 2  # 4096 blocks: 32 encoder tiles of 128
+    assert small // 128 < simds
+    assert tiles([enc(512)]) == small // 64
+    assert tiles([dec(512)]) == small // 64
+    assert tiles([enc(512), dec(512)]) == 2 * small // 64
+    big = (4096 // 8) ** 2  # 262144 blocks per image
+    assert 16 * big // 128 >= simds
+    assert tiles([enc(4096)] * 16) == 16 * big // 128
+    assert tiles([enc(4096)] * 16 + [dec(512)]) == 16 * big // 128 + small // 64
+    assert tiles([fwd(4096)] * 16) == 16 * big // 64
+
+
 def test_graph_replays_equal_direct_launch(tdct):
     R = Ragged(tdct, seed=6)
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs)
