@@ -1,7 +1,7 @@
 // Serving form: a request loop in front of the persistent batch kernel.
 //
-// submit() only records a request. One scheduler thread owns everything
-// else, in this order on every pass:
+// submit() records a request. One scheduler thread does everything else, in
+// this order on every pass:
 //   1. completion: a stream slot whose event has fired marks its requests
 //      done (the host clock at that moment is the completion time);
 //   2. admission: waiting requests, oldest first, reserve their output bytes
@@ -14,7 +14,11 @@
 // Several slots may be in flight at once, so requests that arrive while
 // others run are admitted and launched as memory and slots free up, and their
 // kernels overlap on the device (continuous batching). With batching = 0 the
-// same loop launches each request on its own (the per-image baseline).
+// same loop launches each request on its own (the per-image baseline). One
+// shortcut: a request submitted while the scheduler sleeps (no activity for
+// a while) and nothing else waits is admitted and launched by the submitting
+// thread, which saves the scheduler's wake-up; there is nothing to batch it
+// with, and the scheduler still completes it.
 //
 // Resident mode replaces step 3: admitted requests are written into a queue
 // in host-coherent memory that a resident kernel polls (tdct_resident.hip),
@@ -112,6 +116,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
+    bool launching = false;  // claimed, launch calls in progress without the lock
     double launched_us = 0;
     double fake_done_us = 0;
     bool fake_fail = false;
@@ -173,6 +178,7 @@ struct tdct_server {
     Resident res;
     std::thread worker;
     bool stop = false;
+    bool sleeping = false;  // the scheduler waits on `wake` (no activity for a while)
     uint64_t next_ticket = 1;
     int64_t in_flight = 0;  // submitted and not completed
     int64_t batches = 0;
@@ -237,7 +243,8 @@ int validate_for(const tdct_server* s, const tdct_request& r) {
 }
 
 // Grows a slot's device and pinned buffers to `bytes` (rarely: capacity
-// doubles). Called without the server lock, by the scheduler thread only.
+// doubles). Called without the server lock by the thread that claimed the
+// slot for a launch.
 int ensure_capacity(tdct_server* s, Slot& sl, size_t bytes) {
     if (s->fake) return TDCT_OK;
     if (bytes > sl.dev_cap) {
@@ -447,9 +454,10 @@ void admit(tdct_server* s, double now, bool any_busy) {
 
 // Step 3 of the scheduler: launches admitted requests on free stream slots
 // (up to max_batch and max_batch_px per launch, after the batching window).
-// Unlocks `lk` around each launch; only the scheduler thread launches, so no
-// completion step runs meanwhile. Returns the end of a pending batching
-// window, or -1.
+// Unlocks `lk` around each launch; the slot is marked as launching meanwhile,
+// so a completion step run by the scheduler while another thread launches
+// (a submit that found the scheduler asleep) leaves it alone. Returns the end
+// of a pending batching window, or -1.
 double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
                    std::vector<BatchItem>& items) {
     double next_deadline = -1;
@@ -486,6 +494,7 @@ double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
             sl.fake_done_us = s->now_us() + s->cfg.fake_device_us;
             sl.fake_fail = s->cfg.fake_fail_every > 0 && (s->batches % s->cfg.fake_fail_every) == 0;
         }
+        sl.launching = true;
         lk.unlock();
         int st;
         try {
@@ -495,6 +504,7 @@ double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
             st = TDCT_ENOMEM;
         }
         lk.lock();
+        sl.launching = false;
         if (st) {
             memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
             const double t_now = s->now_us();
@@ -859,6 +869,10 @@ void scheduler(tdct_server* s) {
         bool any_busy = false;
         for (Slot& sl : s->slots) {
             if (!sl.busy) continue;
+            if (sl.launching) {
+                any_busy = true;
+                continue;
+            }
             bool fired;
             int status = TDCT_OK;
             if (s->fake) {
@@ -911,12 +925,14 @@ void scheduler(tdct_server* s) {
                 continue;
             }
         }
+        s->sleeping = true;
         if (next_deadline >= 0) {
             const double dt = std::max(1.0, next_deadline - tnow);
             s->wake.wait_for(lk, std::chrono::microseconds((int64_t)dt));
         } else if (!s->stop) {
             s->wake.wait_for(lk, std::chrono::milliseconds(10));
         }
+        s->sleeping = false;
     }
     if (s->busy_since >= 0) s->st.busy_us += s->now_us() - s->busy_since;
     if (s->cfg.resident) __atomic_fetch_or(s->res.ctrl, kCtrlStop, __ATOMIC_RELEASE);
@@ -988,7 +1004,7 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
 }
 
 static int submit_locked(tdct_server* s, const tdct_request* req, bool release_on_done,
-                         uint64_t* ticket) {
+                         uint64_t* ticket, std::unique_lock<std::mutex>& lk) {
     const int64_t ob = output_bytes(*req);
     if (Arena::round(reserve_bytes(*req)) > s->arena->size() ||
         (s->cfg.resident && request_tiles(*req) > (int64_t)s->res.ring_tiles)) {
@@ -1012,6 +1028,15 @@ static int submit_locked(tdct_server* s, const tdct_request* req, bool release_o
         // preceding it (the scheduler still watches the done flags).
         admit(s, q.submit_us, true);
         resident_publish(s, q.submit_us);
+    } else if (s->sleeping && s->waiting.size() == 1 && s->admitted.empty()) {
+        // The scheduler is asleep and this request is the only one: there is
+        // nothing to batch it with, so it is admitted and launched here
+        // rather than after the scheduler's wake-up (the scheduler, woken
+        // once the submit returns, still watches its completion).
+        const double now = q.submit_us;
+        admit(s, now, false);
+        std::vector<BatchItem> items;
+        launch_step(s, lk, now, items);
     }
     return TDCT_OK;
 }
@@ -1022,9 +1047,9 @@ static int submit_now(tdct_server* s, const tdct_request* req, bool release_on_d
                       uint64_t* ticket) {
     int st;
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        std::unique_lock<std::mutex> lk(s->mu);
         if (s->stop) return TDCT_EBUSY;
-        st = submit_locked(s, req, release_on_done, ticket);
+        st = submit_locked(s, req, release_on_done, ticket, lk);
     }
     s->wake.notify_one();
     return st;
