@@ -313,7 +313,10 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
     finally:
         tdct.tdct_plan_free(plan)
     del src, coef, dst
+    gbs = 4 * px / graph_s / 1e9
     return {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(gbs / 8000.0, 4)},
             "graph_gpx_s": round(px / graph_s / 1e9, 2), "graph_ms": round(graph_s * 1e3, 3),
             "per_image_gpx_s": round(px / per_s / 1e9, 2), "per_image_ms": round(per_s * 1e3, 3),
             "per_image_graph_gpx_s": round(px / per_graph_s / 1e9, 2),
