@@ -103,6 +103,34 @@ def test_fake_server_completes_everything_and_counts(tdct):
         tdct.tdct_server_destroy(s)
 
 
+def test_fake_server_launches_lone_requests_from_submit(tdct):
+    """Requests spaced wider than the scheduler's polling window find it
+    asleep; each is admitted and launched by the submitting thread and still
+    completed by the scheduler, alone in its batch. Bursts in between go
+    through the scheduler and batch as before."""
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 24, streams=2, max_batch=8, fake_device_us=300))
+    try:
+        lone = []
+        for k in range(6):
+            time.sleep(0.006)  # past the 2 ms polling window: the scheduler sleeps
+            lone.append(tdct.tdct_server_submit(s, _req(tdct, k % 2, 64, 32)))
+            assert tdct.tdct_server_wait(s, lone[-1]).status == tdct.TDCT_OK
+        time.sleep(0.006)
+        burst = [tdct.tdct_server_submit(s, _req(tdct, k % 2, 64, 32)) for k in range(24)]
+        tdct.tdct_server_drain(s)
+        for t in lone:
+            r = tdct.tdct_server_poll(s, t)
+            assert r.status == tdct.TDCT_OK and r.batch_size == 1 and r.done_us >= r.submit_us
+        sizes = [tdct.tdct_server_poll(s, t).batch_size for t in burst]
+        assert all(tdct.tdct_server_poll(s, t).status == tdct.TDCT_OK for t in burst)
+        assert max(sizes) > 1  # the burst was batched
+        st = tdct.tdct_server_stats(s)
+        assert st["completed"] == 30 and st["failed"] == 0
+        assert tdct.tdct_server_last_error(s) == ""
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
 def test_fake_server_admission_never_exceeds_budget(tdct):
     budget = 3 * 64 * 64 * 2  # room for three encode outputs of 64 x 64
     s = tdct.tdct_server_create(tdct.server_cfg(budget, streams=4, max_batch=8, fake_device_us=300))
