@@ -92,6 +92,15 @@ def make_large_batch(tdct, torch, n, side):
                 enc=enc, dec=dec, pixels=n * side * side)
 
 
+def parse_tune(text):
+    """'WPG,GPC,TW' or 'WPG,GPC,TW,XCD' as a launch-shape dict."""
+    v = [int(x) for x in text.split(",")]
+    if len(v) not in (3, 4):
+        raise SystemExit("a launch shape is WPG,GPC,TW[,XCD_REMAP]: %r" % text)
+    return dict(waves_per_group=v[0], groups_per_cu=v[1], tile_waves=v[2],
+                xcd_remap=v[3] if len(v) == 4 else 0)
+
+
 def time_steps(tdct, torch, pe, pd, steps, warmup, stream):
     for _ in range(warmup):
         tdct.tdct_batch_run(pe, stream)
@@ -690,14 +699,14 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
     ap.add_argument("--tune", default="",
                     help="fixed launch shapes instead of autotuning: "
-                         "'WPG,GPC,TW:WPG,GPC,TW' for the encoder and the decoder")
+                         "'WPG,GPC,TW[,XCD]:WPG,GPC,TW[,XCD]' for the encoder and the decoder")
     ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--quality", action="store_true",
                     help="also run the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--legs", default="",
                     help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--fused-tune", default="",
-                    help="fixed launch shape 'WPG,GPC,TW' for the fused round trip")
+                    help="fixed launch shape 'WPG,GPC,TW[,XCD]' for the fused round trip")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -737,8 +746,7 @@ def main():
     fixed = [None, None]
     if args.tune:
         for k, part in enumerate(args.tune.split(":")):
-            a, b, c = (int(x) for x in part.split(","))
-            fixed[k] = dict(waves_per_group=a, groups_per_cu=b, tile_waves=c)
+            fixed[k] = parse_tune(part)
     pe = tdct.tdct_batch_plan(W["enc"], W["qs"], tune=fixed[0])
     pd = tdct.tdct_batch_plan(W["dec"], W["qs"], tune=fixed[1])
     try:
@@ -802,8 +810,7 @@ def main():
         log("fused round-trip leg...")
         ft = None
         if args.fused_tune:
-            a, b, c = (int(x) for x in args.fused_tune.split(","))
-            ft = dict(waves_per_group=a, groups_per_cu=b, tile_waves=c)
+            ft = parse_tune(args.fused_tune)
         result["fused_roundtrip"] = fused_leg(tdct, torch, W, stream, tune=ft)
     if want("per_image"):
         log("per-image launches of the same batch...")

@@ -149,13 +149,14 @@ typedef struct {
 
 /* Launch shape of the persistent kernel. Zero fields take the defaults:
  * one wave per workgroup, a full grid (groups_per_cu 4096: the grid is
- * capped at one wave per tile step) and one tile per step. */
+ * capped at one wave per tile step), one tile per step, no XCD remap. */
 typedef struct {
     int32_t waves_per_group; /* 1, 2, 4 or 8 (64-lane waves per workgroup) */
     int32_t groups_per_cu;   /* workgroups per compute unit; grid = CUs * this, capped at the
                                 workgroups needed for one tile step per wave */
     int32_t tile_waves;      /* consecutive wave-tiles one wave takes per step (1, 2, 4) */
-    int32_t reserved;
+    int32_t xcd_remap;       /* 0 or 1: workgroup b runs on XCD b mod 8; with 1, the
+                                workgroups of each XCD take one contiguous range of tiles */
 } tdct_tune;
 
 typedef struct {

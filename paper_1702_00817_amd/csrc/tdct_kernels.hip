@@ -38,15 +38,29 @@ __global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QCons
 // descriptor and quantiser constants are read with scalar loads (the tile is
 // image-uniform, so they are the same for the whole wave). OPS is the set of
 // ops the plan contains; single-op plans get a kernel with just that path.
+// Workgroups are dealt to the XCDs in turn (workgroup b runs on XCD
+// b mod kXcds). With xcd_remap set, workgroup b takes the place of
+// workgroup xcd * per + b / kXcds in the launch order, so that the
+// workgroups of each XCD work through one contiguous range of tiles
+// (a bijection on [0, n) also when n is not a multiple of kXcds).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t n) {
+    const uint32_t xcd = b % kXcds, slot = b / kXcds;
+    const uint32_t per = (n + kXcds - 1) / kXcds, tall = n % kXcds ? n % kXcds : kXcds;
+    return xcd < tall ? xcd * per + slot : tall * per + (xcd - tall) * (per - 1) + slot;
+}
+
 template <int OPS>
 __global__ __launch_bounds__(512) void batch_kernel(const Tile* __restrict__ tiles,
                                                      const ImgDesc* __restrict__ imgs,
                                                      const QConst* __restrict__ qcs,
-                                                     uint32_t ntiles, uint32_t tile_waves) {
+                                                     uint32_t ntiles, uint32_t tile_waves,
+                                                     uint32_t xcd_remap) {
     extern __shared__ v4u lds[];
     v4u* wl = lds + (threadIdx.x >> 6) * (lds_wave_bytes(OPS) / 16);
     const uint32_t wpg = blockDim.x >> 6;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpg + (threadIdx.x >> 6));
+    const uint32_t group = xcd_remap ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(group * wpg + (threadIdx.x >> 6));
     const uint32_t nwaves = gridDim.x * wpg;
     const uint32_t lane = threadIdx.x & 63;
     // A wave takes `tile_waves` consecutive tiles per step.
@@ -244,7 +258,7 @@ static int launch_batch_ops(const Tile* tiles, const ImgDesc* imgs, const QConst
     int st = allow_lds(batch_kernel<OPS>, lds);
     if (st) return st;
     hipLaunchKernelGGL(batch_kernel<OPS>, dim3(grid), dim3(64 * wpg), lds, stream, tiles, imgs, qcs,
-                       ntiles, tw);
+                       ntiles, tw, (uint32_t)(tune.xcd_remap != 0));
     return check_launch("batch kernel launch");
 }
 

@@ -69,7 +69,7 @@ def test_argument_errors_need_no_device(tdct):
     d.keep, d.op = 64, 9
     assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, None, r(h)) == tdct.TDCT_EINVAL
     d.op = tdct.OP_ENCODE
-    for bad_tune in ((3, 1, 1, 0), (16, 1, 1, 0), (4, 5000, 1, 0), (4, 1, 3, 0)):
+    for bad_tune in ((3, 1, 1, 0), (16, 1, 1, 0), (4, 5000, 1, 0), (4, 1, 3, 0), (4, 1, 1, 2)):
         t = tdct.tdct_tune(*bad_tune)
         assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, r(t), r(h)) == tdct.TDCT_EINVAL
 

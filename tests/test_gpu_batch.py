@@ -125,7 +125,8 @@ def test_tile_size_and_default_shape_of_plans(tdct):
             info = tdct.tdct_plan_info_get(plan)
         finally:
             tdct.tdct_plan_free(plan)
-        assert info["tune"] == {"waves_per_group": 1, "groups_per_cu": 4096, "tile_waves": 1}
+        assert info["tune"] == {"waves_per_group": 1, "groups_per_cu": 4096, "tile_waves": 1,
+                                "xcd_remap": 0}
         return info["tiles"]
 
     def enc(side):
@@ -166,7 +167,10 @@ def test_graph_replays_equal_direct_launch(tdct):
                                   dict(waves_per_group=2, groups_per_cu=3, tile_waves=2),
                                   dict(waves_per_group=8, groups_per_cu=4, tile_waves=4),
                                   dict(waves_per_group=8, groups_per_cu=4096, tile_waves=1),
-                                  dict(waves_per_group=1, groups_per_cu=4096, tile_waves=2)])
+                                  dict(waves_per_group=1, groups_per_cu=4096, tile_waves=2),
+                                  dict(waves_per_group=1, groups_per_cu=4096, tile_waves=1, xcd_remap=1),
+                                  dict(waves_per_group=4, groups_per_cu=1, tile_waves=2, xcd_remap=1),
+                                  dict(waves_per_group=2, groups_per_cu=3, tile_waves=4, xcd_remap=1)])
 def test_every_launch_shape_gives_same_bytes(tdct, tune):
     R = Ragged(tdct, seed=7)
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs, tune=tune)
@@ -195,9 +199,14 @@ def test_autotuner_result_and_per_image_launches(tdct):
 
 # ---- full-size workloads ------------------------------------------------------
 
-def test_large_batch_64_images_4096(tdct):
+@pytest.mark.parametrize("tune", [None,
+                                  dict(waves_per_group=1, groups_per_cu=4096, tile_waves=1, xcd_remap=1),
+                                  dict(waves_per_group=4, groups_per_cu=1, tile_waves=2, xcd_remap=1)])
+def test_large_batch_64_images_4096(tdct, tune):
     """64 images of 4096 x 4096, per-image Q = 1 + s (i + j): one persistent
-    encode launch and one decode launch, as timed by the benchmark."""
+    encode launch and one decode launch, as timed by the benchmark, in the
+    default launch shape and in the XCD-remapped shapes the autotuner picks
+    for them."""
     import torch
     sizes, seeds, qs = synth.large_batch_spec()
     n, side = len(sizes), sizes[0][0]
@@ -211,7 +220,7 @@ def test_large_batch_64_images_4096(tdct):
                            src_stride=side, coef=coef[i]) for i in range(n)]
     dec = [tdct.image_desc(tdct.OP_DECODE, side, side, qtab=i, coef=coef[i], dst=dst[i],
                            dst_stride=side) for i in range(n)]
-    pe, pd = tdct.tdct_batch_plan(enc, qs), tdct.tdct_batch_plan(dec, qs)
+    pe, pd = tdct.tdct_batch_plan(enc, qs, tune=tune), tdct.tdct_batch_plan(dec, qs, tune=tune)
     try:
         tdct.tdct_batch_run(pe)
         tdct.tdct_batch_run(pd)
@@ -236,7 +245,8 @@ def test_large_batch_64_images_4096(tdct):
 
 
 @pytest.mark.parametrize("tune", [dict(waves_per_group=8, groups_per_cu=4096, tile_waves=2),
-                                  dict(waves_per_group=4, groups_per_cu=4096, tile_waves=1)])
+                                  dict(waves_per_group=4, groups_per_cu=4096, tile_waves=1),
+                                  dict(waves_per_group=4, groups_per_cu=1, tile_waves=2, xcd_remap=1)])
 def test_forward_int32_64_images_4096(tdct, tune):
     """The int32 forward transform alone over the 64 images of 4096 x 4096
     (4 GiB of coefficients), in the launch shapes the autotuner picks for
