@@ -201,4 +201,17 @@ __host__ __device__ inline int tile_blocks(int op) {
     return (op == OP_DECODE || op == OP_FORWARD) ? kDecTileBlocks : kEncTileBlocks;
 }
 
+// Workgroups are dealt to the XCDs in turn (workgroup b runs on XCD
+// b mod kXcds). xcd_order(b, n) is the place workgroup b takes in the tile
+// order when each XCD's workgroups work through one contiguous range of
+// tiles: XCD x's workgroups get x's range in launch order. A bijection on
+// [0, n), also when n is not a multiple of kXcds (the first n mod kXcds
+// XCDs get one workgroup more).
+constexpr uint32_t kXcds = 8;
+__host__ __device__ inline uint32_t xcd_order(uint32_t b, uint32_t n) {
+    const uint32_t xcd = b % kXcds, slot = b / kXcds;
+    const uint32_t per = (n + kXcds - 1) / kXcds, tall = n % kXcds ? n % kXcds : kXcds;
+    return xcd < tall ? xcd * per + slot : tall * per + (xcd - tall) * (per - 1) + slot;
+}
+
 }  // namespace tdct

@@ -38,18 +38,6 @@ __global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QCons
 // descriptor and quantiser constants are read with scalar loads (the tile is
 // image-uniform, so they are the same for the whole wave). OPS is the set of
 // ops the plan contains; single-op plans get a kernel with just that path.
-// Workgroups are dealt to the XCDs in turn (workgroup b runs on XCD
-// b mod kXcds). With xcd_remap set, workgroup b takes the place of
-// workgroup xcd * per + b / kXcds in the launch order, so that the
-// workgroups of each XCD work through one contiguous range of tiles
-// (a bijection on [0, n) also when n is not a multiple of kXcds).
-constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t n) {
-    const uint32_t xcd = b % kXcds, slot = b / kXcds;
-    const uint32_t per = (n + kXcds - 1) / kXcds, tall = n % kXcds ? n % kXcds : kXcds;
-    return xcd < tall ? xcd * per + slot : tall * per + (xcd - tall) * (per - 1) + slot;
-}
-
 template <int OPS>
 __global__ __launch_bounds__(512) void batch_kernel(const Tile* __restrict__ tiles,
                                                      const ImgDesc* __restrict__ imgs,

@@ -100,4 +100,9 @@ void hc_quant_lanes(int32_t Q, int32_t s, int32_t y0, int32_t n, int8_t* out8, i
     }
 }
 
+// out[b] = the tile-order place of workgroup b of n under the XCD remap.
+void hc_xcd_order(uint32_t n, uint32_t* out) {
+    for (uint32_t b = 0; b < n; ++b) out[b] = tdct::xcd_order(b, n);
+}
+
 }  // extern "C"

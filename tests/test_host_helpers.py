@@ -32,6 +32,7 @@ def hc():
     L.hc_shifts.argtypes = [P]
     L.hc_quant.argtypes = [ctypes.c_int32] * 4 + [P]
     L.hc_quant_lanes.argtypes = [ctypes.c_int32] * 4 + [P, P]
+    L.hc_xcd_order.argtypes = [ctypes.c_uint32, P]
     return L
 
 
@@ -139,3 +140,19 @@ def test_quantiser_lane_forms_store_the_right_bits(hc, oracle_mod):
             exp = oracle_mod.round_div_array(y << s, int(Q))
             assert np.array_equal(o16.astype(np.int64), exp)
             assert np.array_equal(o8.astype(np.int64), np.clip(exp, -128, 127))
+
+
+@pytest.mark.parametrize("n", list(range(1, 40)) + [255, 256, 257, 1023, 131072, 131075, 402064])
+def test_xcd_order_is_a_bijection_with_one_contiguous_range_per_xcd(hc, n):
+    """The batch kernel's XCD remap: workgroup b runs on XCD b % 8; its place
+    in the tile order must be a permutation of [0, n) under which the
+    workgroups of each XCD, in launch order, take one contiguous range, the
+    ranges following XCD order."""
+    out = np.zeros(n, np.uint32)
+    hc.hc_xcd_order(n, out.ctypes.data)
+    assert np.array_equal(np.sort(out), np.arange(n, dtype=np.uint32))
+    nxt = 0
+    for x in range(8):
+        places = out[x::8]  # XCD x's workgroups in launch order
+        assert np.array_equal(places, np.arange(nxt, nxt + places.size, dtype=np.uint32))
+        nxt += places.size
