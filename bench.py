@@ -712,9 +712,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; the codec shards by image with no "
-              "cross-GPU exchange (see the design notes), so --gpus %d is not run." % args.gpus,
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the codec shards by image (or block range) with "
+              "no cross-GPU exchange, so each GPU runs this same step on its share; "
+              "--gpus %d is not run." % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -23,8 +23,9 @@
  *   - reconstruction (Section 3): W'_ij = q_ij * Q_ij, S = T^t * W' * T and
  *     pixel = clamp(floor((S + 32) / 64) + 128, 0, 255).
  * The integer conventions (level shift, the scale 64, both rounding rules,
- * the clamp) are not fixed by the paper; the readings are listed in the
- * design notes. Every accumulator is 64-bit, so nothing here can overflow.
+ * the clamp) are not fixed by the paper; the oracle takes the readings
+ * written out above. Every accumulator is 64-bit, so nothing here can
+ * overflow.
  *
  * Block (bx, by) of a w x h plane covers rows 8*by..8*by+7 and columns
  * 8*bx..8*bx+7; blocks are numbered in raster order b = by * (w/8) + bx and
