@@ -186,7 +186,8 @@ def test_autotuner_result_and_per_image_launches(tdct):
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs)
     try:
         best = tdct.tdct_autotune(plan, reps=1)
-        assert best["waves_per_group"] in (1, 2, 4, 8)
+        assert best["waves_per_group"] in (1, 2, 4, 8) and best["xcd_remap"] in (0, 1)
+        assert tdct.tdct_plan_info_get(plan)["tune"] == best  # the plan keeps the winner
         R.clear()
         tdct.tdct_batch_run(plan)
         R.check(tdct)
