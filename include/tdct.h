@@ -30,7 +30,8 @@
  *    stream) and return once the work is enqueued.
  *  - Errors are returned as tdct_status codes; no exception crosses the ABI.
  *    TDCT_EDEVICE means a HIP runtime call failed; tdct_last_error() then
- *    returns its text for the calling thread.
+ *    returns its text for the calling thread. A call that runs out of host
+ *    memory returns TDCT_ENOMEM (and leaves nothing half-built).
  *  - Planes: w and h are positive multiples of 8 (TDCT_EDIM otherwise),
  *    at most 65536 each, the row stride in bytes is >= w. Any pixel pointer
  *    and stride are accepted; 8- and 16-byte aligned ones take faster loads.
@@ -59,7 +60,7 @@ typedef enum {
     TDCT_EINVAL = -1,    /* null pointer, stride < w, misaligned coefficients, bad keep/op */
     TDCT_EDIM = -2,      /* w or h not a positive multiple of 8, or above 65536 */
     TDCT_EQTAB = -3,     /* a Q entry outside [1, 4095] */
-    TDCT_ENOMEM = -4,    /* device allocation failed, or a request larger than the budget */
+    TDCT_ENOMEM = -4,    /* device or host allocation failed, or a request larger than the budget */
     TDCT_EDEVICE = -5,   /* a HIP runtime call failed (see tdct_last_error) */
     TDCT_EBUSY = -6,     /* result not ready yet, or the server is shutting down */
     TDCT_ENOTFOUND = -7  /* unknown or already released ticket */
