@@ -34,17 +34,19 @@ class Ragged:
     """A mixed batch: every op, uneven sizes (odd blocks per row, strips,
     single blocks), strides wider than the image, several Q tables."""
 
-    def __init__(self, tdct, seed=5):
+    def __init__(self, tdct, seed=5, big=False):
         import torch
         rng = np.random.default_rng(seed)
         self.qtabs = [synth.qtable(1, s) for s in (1, 3, 8)] + [rng.integers(1, 4096, 64).astype(np.uint16)]
         sizes = [(8, 8), (24, 16), (136, 72), (1024, 64), (8, 1024), (520, 48), (40, 40), (2048, 24)]
         sizes += [(8 * int(a), 8 * int(b)) for a, b in rng.integers(1, 40, size=(24, 2))]
+        if big:  # enough blocks for 128-block encoder tiles (a small plan uses 64)
+            sizes = [(4096, 2048)] + sizes
         self.items = []
         ops = [tdct.OP_ENCODE, tdct.OP_DECODE, tdct.OP_ROUNDTRIP, tdct.OP_ENCODE_I8ZZ, tdct.OP_FORWARD]
         self.keep_alive = []
         for k, (w, h) in enumerate(sizes):
-            op = ops[k % len(ops)]
+            op = ops[(k + seed) % len(ops)]
             stride = w + (8 * (k % 3)) + (3 if k % 7 == 3 else 0)
             img = synth.textured(w, h, 500 + k, stride=stride)
             qt = k % len(self.qtabs)
@@ -175,6 +177,27 @@ def test_every_launch_shape_gives_same_bytes(tdct, tune):
     R = Ragged(tdct, seed=7)
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs, tune=tune)
     try:
+        tdct.tdct_batch_run(plan)
+        R.check(tdct)
+    finally:
+        tdct.tdct_plan_free(plan)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_plans_and_launch_shapes(tdct, seed):
+    """Seeded mixed plans (every op, uneven sizes and strides; odd seeds add
+    a 4096 x 2048 image, which makes the plan large enough for 128-block
+    encoder tiles) in a random launch shape, XCD order included, against the
+    oracle."""
+    rng = np.random.default_rng(9000 + seed)
+    tune = dict(waves_per_group=int(rng.choice([1, 2, 4, 8])),
+                groups_per_cu=int(rng.choice([1, 2, 3, 4, 8, 16, 4096])),
+                tile_waves=int(rng.choice([1, 2, 4])), xcd_remap=int(rng.integers(2)))
+    print("seed", seed, "tune", tune, flush=True)
+    R = Ragged(tdct, seed=100 + seed, big=seed % 2 == 1)
+    plan = tdct.tdct_batch_plan(R.descs, R.qtabs, tune=tune)
+    try:
+        assert tdct.tdct_plan_info_get(plan)["tune"] == tune
         tdct.tdct_batch_run(plan)
         R.check(tdct)
     finally:
