@@ -179,7 +179,8 @@ typedef struct tdct_plan tdct_plan;
 int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
                     int32_t nq, const tdct_tune* tune_or_null, tdct_plan** out);
 
-/* One persistent launch over every tile of the plan on `stream`. */
+/* One persistent launch over every tile of the plan on `stream` (a plan of
+ * no images launches nothing; run, graph and autotune return TDCT_OK). */
 int tdct_batch_run(tdct_plan* plan, void* stream);
 
 /* Same work as tdct_batch_run, through a hipGraph captured on the first

@@ -237,6 +237,7 @@ int tdct_batch_run(tdct_plan* p, void* stream) {
 
 int tdct_batch_graph(tdct_plan* p, void* stream) {
     if (!p) return TDCT_EINVAL;
+    if (p->tiles.empty()) return TDCT_OK;  // an empty plan launches nothing
     hipError_t e;
     if (!p->exec) {
         if (!p->capture_stream) {
@@ -281,6 +282,10 @@ int tdct_batch_graph(tdct_plan* p, void* stream) {
 int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
     return abi_call([&]() -> int {
         if (!p || reps < 1) return TDCT_EINVAL;
+        if (p->tiles.empty()) {  // nothing to time: the plan keeps its shape
+            if (best) *best = p->tune;
+            return TDCT_OK;
+        }
         hipStream_t s = (hipStream_t)stream;
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return TDCT_EDEVICE;

@@ -152,6 +152,20 @@ def test_tile_size_and_default_shape_of_plans(tdct):
     assert tiles([fwd(4096)] * 16) == 16 * big // 64
 
 
+def test_empty_plan_is_a_no_op(tdct):
+    plan = tdct.tdct_batch_plan([], [np.ones(64, np.uint16)])
+    try:
+        info = tdct.tdct_plan_info_get(plan)
+        assert info["images"] == 0 and info["tiles"] == 0 and info["blocks"] == 0
+        tdct.tdct_batch_run(plan)
+        tdct.tdct_batch_graph(plan)
+        assert tdct.tdct_autotune(plan, reps=1) == info["tune"]
+        tdct.tdct_run_per_image([], [np.ones(64, np.uint16)])
+        sync()
+    finally:
+        tdct.tdct_plan_free(plan)
+
+
 def test_graph_replays_equal_direct_launch(tdct):
     R = Ragged(tdct, seed=6)
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs)
