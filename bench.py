@@ -93,12 +93,12 @@ def make_large_batch(tdct, torch, n, side):
 
 
 def parse_tune(text):
-    """'WPG,GPC,TW' or 'WPG,GPC,TW,XCD' as a launch-shape dict."""
+    """'WPG,GPC,TW[,XCD[,PIXEL_CACHE]]' as a launch-shape dict."""
     v = [int(x) for x in text.split(",")]
-    if len(v) not in (3, 4):
-        raise SystemExit("a launch shape is WPG,GPC,TW[,XCD_REMAP]: %r" % text)
+    if len(v) not in (3, 4, 5):
+        raise SystemExit("a launch shape is WPG,GPC,TW[,XCD_REMAP[,PIXEL_CACHE]]: %r" % text)
     return dict(waves_per_group=v[0], groups_per_cu=v[1], tile_waves=v[2],
-                xcd_remap=v[3] if len(v) == 4 else 0)
+                xcd_remap=v[3] if len(v) >= 4 else 0, pixel_cache=v[4] if len(v) == 5 else 0)
 
 
 def time_steps(tdct, torch, pe, pd, steps, warmup, stream):
@@ -699,14 +699,15 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
     ap.add_argument("--tune", default="",
                     help="fixed launch shapes instead of autotuning: "
-                         "'WPG,GPC,TW[,XCD]:WPG,GPC,TW[,XCD]' for the encoder and the decoder")
+                         "'WPG,GPC,TW[,XCD[,PC]]:WPG,GPC,TW[,XCD[,PC]]' for the encoder and the "
+                         "decoder (PC: cached pixel accesses)")
     ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--quality", action="store_true",
                     help="also run the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--legs", default="",
                     help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--fused-tune", default="",
-                    help="fixed launch shape 'WPG,GPC,TW[,XCD]' for the fused round trip")
+                    help="fixed launch shape 'WPG,GPC,TW[,XCD[,PC]]' for the fused round trip")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

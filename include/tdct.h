@@ -150,7 +150,8 @@ typedef struct {
 
 /* Launch shape of the persistent kernel. Zero fields take the defaults:
  * one wave per workgroup, a full grid (groups_per_cu 4096: the grid is
- * capped at one wave per tile step), one tile per step, no XCD remap. */
+ * capped at one wave per tile step), one tile per step, no XCD remap,
+ * streaming pixel accesses. */
 typedef struct {
     int32_t waves_per_group; /* 1, 2, 4 or 8 (64-lane waves per workgroup) */
     int32_t groups_per_cu;   /* workgroups per compute unit; grid = CUs * this, capped at the
@@ -158,6 +159,9 @@ typedef struct {
     int32_t tile_waves;      /* consecutive wave-tiles one wave takes per step (1, 2, 4) */
     int32_t xcd_remap;       /* 0 or 1: workgroup b runs on XCD b mod 8; with 1, the
                                 workgroups of each XCD take one contiguous range of tiles */
+    int32_t pixel_cache;     /* 0 or 1: pixel-plane loads and stores are non-temporal (0) or
+                                ordinary cached accesses (1); coefficients always stream.
+                                Only speed differs, never the output */
 } tdct_tune;
 
 typedef struct {
@@ -214,7 +218,7 @@ typedef struct {
     int64_t max_batch_px;  /* a batch stops growing once it holds this many pixels, so
                               small requests do not wait for a huge one (0 = no cap) */
     tdct_tune tune;        /* launch shape of batch launches (zero fields: one wave per
-                              workgroup, one tile per wave) */
+                              workgroup, one tile per wave; out of range: TDCT_EINVAL) */
     int32_t fake_device_us; /* > 0: no GPU at all -- outputs live in host memory and a
                                batch "completes" this many microseconds after launch
                                (exercises admission and batching on a CPU) */

@@ -55,11 +55,13 @@ class tdct_image_desc(ctypes.Structure):
 
 class tdct_tune(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32),
-                ("tile_waves", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+                ("tile_waves", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("pixel_cache", ctypes.c_int32)]
 
     def as_dict(self):
         return {"waves_per_group": self.waves_per_group, "groups_per_cu": self.groups_per_cu,
-                "tile_waves": self.tile_waves, "xcd_remap": self.xcd_remap}
+                "tile_waves": self.tile_waves, "xcd_remap": self.xcd_remap,
+                "pixel_cache": self.pixel_cache}
 
 
 class tdct_plan_info(ctypes.Structure):

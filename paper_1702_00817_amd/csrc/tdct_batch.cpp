@@ -43,12 +43,10 @@ struct tdct_plan {
     hipStream_t capture_stream = nullptr;
 };
 
-namespace {
-
 // One wave per workgroup and one tile per wave over a full grid: a small
 // plan's waves land on as many CUs as there are waves, and on large plans
 // the autotuner's pick is a full grid too.
-tdct_tune default_tune() {
+static tdct_tune default_tune() {
     tdct_tune t{};
     t.waves_per_group = 1;
     t.groups_per_cu = 4096;
@@ -56,22 +54,26 @@ tdct_tune default_tune() {
     return t;
 }
 
-int normalise_tune(const tdct_tune* in, tdct_tune* out) {
+int tdct::normalise_tune(const tdct_tune* in, tdct_tune* out) {
     tdct_tune t = default_tune();
     if (in) {
         if (in->waves_per_group) t.waves_per_group = in->waves_per_group;
         if (in->groups_per_cu) t.groups_per_cu = in->groups_per_cu;
         if (in->tile_waves) t.tile_waves = in->tile_waves;
         t.xcd_remap = in->xcd_remap;
+        t.pixel_cache = in->pixel_cache;
     }
     const int w = t.waves_per_group;
     if (!(w == 1 || w == 2 || w == 4 || w == 8)) return TDCT_EINVAL;
     if (t.groups_per_cu < 1 || t.groups_per_cu > 4096) return TDCT_EINVAL;
     if (!(t.tile_waves == 1 || t.tile_waves == 2 || t.tile_waves == 4)) return TDCT_EINVAL;
     if (t.xcd_remap != 0 && t.xcd_remap != 1) return TDCT_EINVAL;
+    if (t.pixel_cache != 0 && t.pixel_cache != 1) return TDCT_EINVAL;
     *out = t;
     return TDCT_OK;
 }
+
+namespace {
 
 int validate_image(const tdct_image_desc& im, int32_t nq) {
     switch (im.op) {
@@ -324,32 +326,35 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
         int st = TDCT_OK;
         // Stage 1: every launch shape (persistent grids of 1..16 resident waves
         // per CU, and a full grid where every wave takes tile_waves tiles and
-        // exits; tiles in launch order or one contiguous range per XCD), one
-        // warm-up and `reps` timed launches each.
+        // exits; tiles in launch order or one contiguous range per XCD;
+        // streaming or cached pixel accesses), one warm-up and `reps` timed
+        // launches each.
         const int wpgs[] = {1, 2, 4, 8};
         const int gpcs[] = {1, 2, 4, 8, 16, 4096};
         const int tws[] = {1, 2};
-        for (int remap = 0; remap < 2; ++remap)
-            for (int wpg : wpgs)
-                for (int gpc : gpcs)
-                    for (int tw : tws) {
-                        // at most 32 waves per CU are resident
-                        if (gpc < 4096 && wpg * gpc > 32) continue;
-                        if (batch_lds_bytes(p->ops, wpg) > 160 * 1024) continue;
-                        tdct_tune t{};
-                        t.waves_per_group = wpg;
-                        t.groups_per_cu = gpc;
-                        t.tile_waves = tw;
-                        t.xcd_remap = remap;
-                        float m = 0;
-                        if ((st = time_one(t, &m))) goto done;  // warm-up
-                        std::vector<float> ms;
-                        for (int r = 0; r < reps; ++r) {
-                            if ((st = time_one(t, &m))) goto done;
-                            ms.push_back(m);
+        for (int cached = 0; cached < 2; ++cached)
+            for (int remap = 0; remap < 2; ++remap)
+                for (int wpg : wpgs)
+                    for (int gpc : gpcs)
+                        for (int tw : tws) {
+                            // at most 32 waves per CU are resident
+                            if (gpc < 4096 && wpg * gpc > 32) continue;
+                            if (batch_lds_bytes(p->ops, wpg) > 160 * 1024) continue;
+                            tdct_tune t{};
+                            t.waves_per_group = wpg;
+                            t.groups_per_cu = gpc;
+                            t.tile_waves = tw;
+                            t.xcd_remap = remap;
+                            t.pixel_cache = cached;
+                            float m = 0;
+                            if ((st = time_one(t, &m))) goto done;  // warm-up
+                            std::vector<float> ms;
+                            for (int r = 0; r < reps; ++r) {
+                                if ((st = time_one(t, &m))) goto done;
+                                ms.push_back(m);
+                            }
+                            cands.push_back({t, median(ms)});
                         }
-                        cands.push_back({t, median(ms)});
-                    }
         // Stage 2: the four fastest again, round-robin over several rounds, so
         // that a drift of the clocks between candidates cannot pick the winner.
         std::sort(cands.begin(), cands.end(),

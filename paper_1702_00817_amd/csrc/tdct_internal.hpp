@@ -46,6 +46,10 @@ int launch_plain_op(int op, const ImgDesc& d, const QConst& qc, hipStream_t stre
 inline bool shrink_tiles(int64_t full_tiles, int num_cus) {
     return full_tiles < 4 * (int64_t)num_cus;
 }
+// A launch shape with zero fields replaced by the defaults (one wave per
+// workgroup, a full grid, one tile per step); TDCT_EINVAL if a field is out
+// of range. `in` may be null (all defaults).
+int normalise_tune(const tdct_tune* in, tdct_tune* out);
 // ops: bit i set when op i occurs in the tiles (selects the kernel instance).
 int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
                  int ops, const tdct_tune& tune, int num_cus, hipStream_t stream);

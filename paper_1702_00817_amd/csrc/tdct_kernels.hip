@@ -38,7 +38,8 @@ __global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QCons
 // descriptor and quantiser constants are read with scalar loads (the tile is
 // image-uniform, so they are the same for the whole wave). OPS is the set of
 // ops the plan contains; single-op plans get a kernel with just that path.
-template <int OPS>
+// CACHED selects the pixel-plane cache policy (ld_px / st_px).
+template <int OPS, bool CACHED>
 __global__ __launch_bounds__(512) void batch_kernel(const Tile* __restrict__ tiles,
                                                      const ImgDesc* __restrict__ imgs,
                                                      const QConst* __restrict__ qcs,
@@ -62,27 +63,27 @@ __global__ __launch_bounds__(512) void batch_kernel(const Tile* __restrict__ til
             switch (op) {
                 case OP_ENCODE:
                     if constexpr ((OPS >> OP_ENCODE) & 1)
-                        run_tile<OP_ENCODE>(d, qc, tl.first_lo, tl.count, lane, wl);
+                        run_tile<OP_ENCODE, CACHED>(d, qc, tl.first_lo, tl.count, lane, wl);
                     break;
                 case OP_DECODE:
                     if constexpr ((OPS >> OP_DECODE) & 1)
-                        run_tile<OP_DECODE>(d, qc, tl.first_lo, tl.count, lane, wl);
+                        run_tile<OP_DECODE, CACHED>(d, qc, tl.first_lo, tl.count, lane, wl);
                     break;
                 case OP_ROUNDTRIP:
                     if constexpr ((OPS >> OP_ROUNDTRIP) & 1)
-                        run_tile<OP_ROUNDTRIP>(d, qc, tl.first_lo, tl.count, lane, wl);
+                        run_tile<OP_ROUNDTRIP, CACHED>(d, qc, tl.first_lo, tl.count, lane, wl);
                     break;
                 case OP_ENCODE_I8ZZ:
                     if constexpr ((OPS >> OP_ENCODE_I8ZZ) & 1)
-                        run_tile<OP_ENCODE_I8ZZ>(d, qc, tl.first_lo, tl.count, lane, wl);
+                        run_tile<OP_ENCODE_I8ZZ, CACHED>(d, qc, tl.first_lo, tl.count, lane, wl);
                     break;
                 case OP_ROUNDTRIP_NC:
                     if constexpr ((OPS >> OP_ROUNDTRIP_NC) & 1)
-                        run_tile<OP_ROUNDTRIP_NC>(d, qc, tl.first_lo, tl.count, lane, wl);
+                        run_tile<OP_ROUNDTRIP_NC, CACHED>(d, qc, tl.first_lo, tl.count, lane, wl);
                     break;
                 default:
                     if constexpr ((OPS >> OP_FORWARD) & 1)
-                        run_tile<OP_FORWARD>(d, qc, tl.first_lo, tl.count, lane, wl);
+                        run_tile<OP_FORWARD, CACHED>(d, qc, tl.first_lo, tl.count, lane, wl);
                     break;
             }
         }
@@ -243,10 +244,11 @@ static int launch_batch_ops(const Tile* tiles, const ImgDesc* imgs, const QConst
     if (grid > need) grid = need;
     if (grid == 0) grid = 1;
     const uint32_t lds = wpg * lds_wave_bytes(OPS);
-    int st = allow_lds(batch_kernel<OPS>, lds);
+    auto kernel = tune.pixel_cache ? batch_kernel<OPS, true> : batch_kernel<OPS, false>;
+    int st = allow_lds(kernel, lds);
     if (st) return st;
-    hipLaunchKernelGGL(batch_kernel<OPS>, dim3(grid), dim3(64 * wpg), lds, stream, tiles, imgs, qcs,
-                       ntiles, tw, (uint32_t)(tune.xcd_remap != 0));
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * wpg), lds, stream, tiles, imgs, qcs, ntiles, tw,
+                       (uint32_t)(tune.xcd_remap != 0));
     return check_launch("batch kernel launch");
 }
 

@@ -956,11 +956,10 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
         if (!s) return TDCT_ENOMEM;
         s->cfg = *cfg;
         if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
-        // The batch form's default shape: one wave per workgroup and one tile
-        // per wave, so a small batch's waves land on as many CUs as there are.
-        if (!s->cfg.tune.waves_per_group) s->cfg.tune.waves_per_group = 1;
-        if (!s->cfg.tune.groups_per_cu) s->cfg.tune.groups_per_cu = 4096;
-        if (!s->cfg.tune.tile_waves) s->cfg.tune.tile_waves = 1;
+        // Zero fields take the batch form's default shape (one wave per
+        // workgroup and one tile per wave, so a small batch's waves land on
+        // as many CUs as there are); out-of-range fields are rejected.
+        if (normalise_tune(&cfg->tune, &s->cfg.tune)) return TDCT_EINVAL;
         s->fake = cfg->fake_device_us > 0;
         s->t0 = Clock::now();
         s->arena = new Arena(cfg->budget_bytes);

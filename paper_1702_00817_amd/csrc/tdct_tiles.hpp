@@ -48,6 +48,28 @@ __device__ __forceinline__ void st_nt2(void* p, v2u v) {
     __builtin_nontemporal_store(v, reinterpret_cast<v2u*>(p));
 }
 
+// Pixel-plane accesses under the cache policy a launch picks. Streaming
+// (CACHED false) marks them non-temporal, as above. Cached ones are ordinary
+// accesses that stay in L2 until evicted: where a tile's pixel rows end
+// inside a 128-byte line (image widths that are not multiples of 128, and
+// tile boundaries inside a row) the neighbouring tile fills the rest of that
+// line, and with both halves meeting in one L2 the line reaches HBM once,
+// whole. Coefficient runs are whole lines and always stream.
+template <bool CACHED>
+__device__ __forceinline__ v2u ld_px(const void* p) {
+    if constexpr (CACHED)
+        return *reinterpret_cast<const v2u*>(p);
+    else
+        return ld_nt2(p);
+}
+template <bool CACHED>
+__device__ __forceinline__ void st_px(void* p, v2u v) {
+    if constexpr (CACHED)
+        *reinterpret_cast<v2u*>(p) = v;
+    else
+        st_nt2(p, v);
+}
+
 // A pointer the compiler cannot place in an address space (read from a
 // table in memory or from LDS) is generic, and generic accesses become FLAT
 // instructions, which also count against the LDS counter: every LDS fence of
@@ -163,12 +185,13 @@ __device__ __forceinline__ void stage_swap(v4u* wl, const v4u (&tmp)[8], uint32_
 
 // ---- pixel side ---------------------------------------------------------------
 
+template <bool CACHED>
 __device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int flags,
                                            uint32_t (&R)[8][2]) {
     if (flags & F_SRC8) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const v2u v = ld_nt2(p + r * stride);
+            const v2u v = ld_px<CACHED>(p + r * stride);
             R[r][0] = v.x;
             R[r][1] = v.y;
         }
@@ -184,11 +207,12 @@ __device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int
     }
 }
 
+template <bool CACHED>
 __device__ __forceinline__ void store_rows8(uint8_t* p, int64_t stride, int flags,
                                             const uint32_t (&R)[8][2]) {
     if (flags & F_DST8) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) st_nt2(p + r * stride, (v2u){R[r][0], R[r][1]});
+        for (int r = 0; r < 8; ++r) st_px<CACHED>(p + r * stride, (v2u){R[r][0], R[r][1]});
     } else {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -256,6 +280,7 @@ struct EncPixels {
     uint32_t A[8][2], B[8][2];
 };
 
+template <bool CACHED = false>
 __device__ __forceinline__ void enc_load(const ImgDesc& d, uint32_t first, uint32_t count,
                                          uint32_t lane, EncPixels& P) {
     const bool va = lane < count, vb = lane + 64u < count;
@@ -266,7 +291,8 @@ __device__ __forceinline__ void enc_load(const ImgDesc& d, uint32_t first, uint3
         const uint8_t* pb = d.src + block_offset(d.src_stride, nbx, bb);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const v2u x = ld_nt2(pa + r * d.src_stride), y = ld_nt2(pb + r * d.src_stride);
+            const v2u x = ld_px<CACHED>(pa + r * d.src_stride);
+            const v2u y = ld_px<CACHED>(pb + r * d.src_stride);
             P.A[r][0] = x.x;
             P.A[r][1] = x.y;
             P.B[r][0] = y.x;
@@ -275,8 +301,10 @@ __device__ __forceinline__ void enc_load(const ImgDesc& d, uint32_t first, uint3
     } else {
 #pragma unroll
         for (int r = 0; r < 8; ++r) P.A[r][0] = P.A[r][1] = P.B[r][0] = P.B[r][1] = 0x80808080u;
-        if (va) load_rows8(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, P.A);
-        if (vb) load_rows8(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, P.B);
+        if (va)
+            load_rows8<CACHED>(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, P.A);
+        if (vb)
+            load_rows8<CACHED>(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, P.B);
     }
 }
 
@@ -287,7 +315,7 @@ struct NoPrefetch {
 };
 
 // Codes the tile whose pixels are in P.
-template <int OP, class QC, class PF>
+template <int OP, bool CACHED = false, class QC, class PF>
 __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl, EncPixels& P,
                                          PF&& prefetch) {
@@ -374,7 +402,7 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
                 W[k] = (int)(__umul24(quant_bits(v[k].x, qc.r[k]), (uint32_t)qc.Q[k]) -
                              ((uint32_t)qc.Q[k] << 22));
             reconstruct(W, px);
-            store_rows8(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+            store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
         }
         if (vb) {
             int W[64];
@@ -383,7 +411,7 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
                 W[k] = (int)(__umul24(quant_bits(v[k].y, qc.r[k]), (uint32_t)qc.Q[k]) -
                              ((uint32_t)qc.Q[k] << 22));
             reconstruct(W, px);
-            store_rows8(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
+            store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
         }
     } else {
         // OP_ENCODE / OP_ROUNDTRIP: int16 coefficients, natural order.
@@ -411,22 +439,22 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
             uint32_t px[8][2];
             if (va) {
                 decode_block(qa, qc, px);
-                store_rows8(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+                store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
             }
             if (vb) {
                 decode_block(qb, qc, px);
-                store_rows8(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
+                store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
             }
         }
     }
 }
 
-template <int OP, class QC>
+template <int OP, bool CACHED = false, class QC>
 __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl) {
     EncPixels P;
-    enc_load(d, first, count, lane, P);
-    enc_tile<OP>(d, qc, first, count, lane, wl, P, NoPrefetch());
+    enc_load<CACHED>(d, first, count, lane, P);
+    enc_tile<OP, CACHED>(d, qc, first, count, lane, wl, P, NoPrefetch());
 }
 
 // ---- decoder tile -----------------------------------------------------------
@@ -445,7 +473,7 @@ __device__ __forceinline__ void dec_load(const ImgDesc& d, uint32_t first, uint3
 }
 
 // Decodes lane's block from its 8 chunks and stores its pixels.
-template <class QC>
+template <bool CACHED = false, class QC>
 __device__ __forceinline__ void dec_finish(const ImgDesc& d, const QC& qc, uint32_t first,
                                            uint32_t lane, const v4u (&mine)[8]) {
     uint32_t qp[32];
@@ -459,7 +487,8 @@ __device__ __forceinline__ void dec_finish(const ImgDesc& d, const QC& qc, uint3
     uint32_t px[8][2];
     decode_block(qp, qc, px);
     const uint32_t b = first + lane;
-    store_rows8(d.dst + block_offset(d.dst_stride, (uint32_t)d.nbx, b), d.dst_stride, d.flags, px);
+    store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, (uint32_t)d.nbx, b), d.dst_stride, d.flags,
+                        px);
 }
 
 template <class QC, class PF>
@@ -473,23 +502,23 @@ __device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_
     dec_finish(d, qc, first, lane, mine);
 }
 
-template <class QC>
+template <bool CACHED = false, class QC>
 __device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl) {
     v4u tmp[8], mine[8];
     stage_load(reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, tmp);
     stage_swap(wl, tmp, lane, mine);
     if (lane >= count) return;
-    dec_finish(d, qc, first, lane, mine);
+    dec_finish<CACHED>(d, qc, first, lane, mine);
 }
 
-template <int OP, class QC>
+template <int OP, bool CACHED = false, class QC>
 __device__ __forceinline__ void run_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl) {
     if constexpr (OP == OP_DECODE)
-        dec_tile(d, qc, first, count, lane, wl);
+        dec_tile<CACHED>(d, qc, first, count, lane, wl);
     else
-        enc_tile<OP>(d, qc, first, count, lane, wl);
+        enc_tile<OP, CACHED>(d, qc, first, count, lane, wl);
 }
 
 // LDS bytes one wave needs for a set of ops (bit i = op i).

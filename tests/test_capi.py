@@ -69,12 +69,31 @@ def test_argument_errors_need_no_device(tdct):
     d.keep, d.op = 64, 9
     assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, None, r(h)) == tdct.TDCT_EINVAL
     d.op = tdct.OP_ENCODE
-    for bad_tune in ((3, 1, 1, 0), (16, 1, 1, 0), (4, 5000, 1, 0), (4, 1, 3, 0), (4, 1, 1, 2)):
+    for bad_tune in ((3, 1, 1, 0, 0), (16, 1, 1, 0, 0), (4, 5000, 1, 0, 0), (4, 1, 3, 0, 0),
+                     (4, 1, 1, 2, 0), (4, 1, 1, 0, 2), (4, 1, 1, 0, -1)):
         t = tdct.tdct_tune(*bad_tune)
         assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, r(t), r(h)) == tdct.TDCT_EINVAL
 
 
 # ---- server logic on the fake device ----------------------------------------
+
+def test_server_tune_is_validated(tdct):
+    """The server's launch shape goes through the same checks as a plan's:
+    out-of-range fields are rejected at create, zero fields take defaults."""
+    for bad in (dict(waves_per_group=3), dict(tile_waves=8), dict(xcd_remap=-1),
+                dict(pixel_cache=2)):
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_create(tdct.server_cfg(1 << 20, fake_device_us=100, tune=bad))
+        assert e.value.status == tdct.TDCT_EINVAL
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 20, fake_device_us=100,
+                                                tune=dict(xcd_remap=1, pixel_cache=1)))
+    try:
+        t = tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 64, 32))
+        tdct.tdct_server_drain(s)
+        assert tdct.tdct_server_poll(s, t).status == tdct.TDCT_OK
+    finally:
+        tdct.tdct_server_destroy(s)
+
 
 def _req(tdct, op, w, h, keep=64):
     return tdct.request(op, w, h, 0x1000, np.ones(64), keep=keep)

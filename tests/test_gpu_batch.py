@@ -128,7 +128,7 @@ def test_tile_size_and_default_shape_of_plans(tdct):
         finally:
             tdct.tdct_plan_free(plan)
         assert info["tune"] == {"waves_per_group": 1, "groups_per_cu": 4096, "tile_waves": 1,
-                                "xcd_remap": 0}
+                                "xcd_remap": 0, "pixel_cache": 0}
         return info["tiles"]
 
     def enc(side):
@@ -186,7 +186,10 @@ def test_graph_replays_equal_direct_launch(tdct):
                                   dict(waves_per_group=1, groups_per_cu=4096, tile_waves=2),
                                   dict(waves_per_group=1, groups_per_cu=4096, tile_waves=1, xcd_remap=1),
                                   dict(waves_per_group=4, groups_per_cu=1, tile_waves=2, xcd_remap=1),
-                                  dict(waves_per_group=2, groups_per_cu=3, tile_waves=4, xcd_remap=1)])
+                                  dict(waves_per_group=2, groups_per_cu=3, tile_waves=4, xcd_remap=1),
+                                  dict(waves_per_group=1, groups_per_cu=4096, tile_waves=1, xcd_remap=1,
+                                       pixel_cache=1),
+                                  dict(waves_per_group=4, groups_per_cu=2, tile_waves=2, pixel_cache=1)])
 def test_every_launch_shape_gives_same_bytes(tdct, tune):
     R = Ragged(tdct, seed=7)
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs, tune=tune)
@@ -201,12 +204,13 @@ def test_every_launch_shape_gives_same_bytes(tdct, tune):
 def test_random_plans_and_launch_shapes(tdct, seed):
     """Seeded mixed plans (every op, uneven sizes and strides; odd seeds add
     a 4096 x 2048 image, which makes the plan large enough for 128-block
-    encoder tiles) in a random launch shape, XCD order included, against the
-    oracle."""
+    encoder tiles) in a random launch shape, XCD order and pixel cache
+    policy included, against the oracle."""
     rng = np.random.default_rng(9000 + seed)
     tune = dict(waves_per_group=int(rng.choice([1, 2, 4, 8])),
                 groups_per_cu=int(rng.choice([1, 2, 3, 4, 8, 16, 4096])),
-                tile_waves=int(rng.choice([1, 2, 4])), xcd_remap=int(rng.integers(2)))
+                tile_waves=int(rng.choice([1, 2, 4])), xcd_remap=int(rng.integers(2)),
+                pixel_cache=int(rng.integers(2)))
     print("seed", seed, "tune", tune, flush=True)
     R = Ragged(tdct, seed=100 + seed, big=seed % 2 == 1)
     plan = tdct.tdct_batch_plan(R.descs, R.qtabs, tune=tune)
@@ -224,6 +228,7 @@ def test_autotuner_result_and_per_image_launches(tdct):
     try:
         best = tdct.tdct_autotune(plan, reps=1)
         assert best["waves_per_group"] in (1, 2, 4, 8) and best["xcd_remap"] in (0, 1)
+        assert best["pixel_cache"] in (0, 1)
         assert tdct.tdct_plan_info_get(plan)["tune"] == best  # the plan keeps the winner
         R.clear()
         tdct.tdct_batch_run(plan)
@@ -239,12 +244,14 @@ def test_autotuner_result_and_per_image_launches(tdct):
 
 @pytest.mark.parametrize("tune", [None,
                                   dict(waves_per_group=1, groups_per_cu=4096, tile_waves=1, xcd_remap=1),
-                                  dict(waves_per_group=4, groups_per_cu=1, tile_waves=2, xcd_remap=1)])
+                                  dict(waves_per_group=4, groups_per_cu=1, tile_waves=2, xcd_remap=1),
+                                  dict(waves_per_group=2, groups_per_cu=4096, tile_waves=1, xcd_remap=1,
+                                       pixel_cache=1)])
 def test_large_batch_64_images_4096(tdct, tune):
     """64 images of 4096 x 4096, per-image Q = 1 + s (i + j): one persistent
     encode launch and one decode launch, as timed by the benchmark, in the
-    default launch shape and in the XCD-remapped shapes the autotuner picks
-    for them."""
+    default launch shape, in the XCD-remapped shapes the autotuner picks for
+    them and with cached pixel accesses."""
     import torch
     sizes, seeds, qs = synth.large_batch_spec()
     n, side = len(sizes), sizes[0][0]
@@ -321,7 +328,8 @@ def test_forward_int32_64_images_4096(tdct, tune):
 def test_ragged_10000_images_one_persistent_launch(tdct):
     """10,000 images with log-uniform sides in [64, 2048]: full encode +
     decode round trip with coefficients, one launch from the block-offset
-    table, replayed through a graph, against one plain launch per image."""
+    table, replayed through a graph, against one plain launch per image and
+    one launch with cached pixel accesses."""
     import torch
     sizes, seeds, qs = synth.ragged_batch_spec()
     n = len(sizes)
@@ -361,6 +369,18 @@ def test_ragged_10000_images_one_persistent_launch(tdct):
               for i, (w, h) in enumerate(sizes)]
         tdct.tdct_run_per_image(d2, qs)
         sync()
+        assert torch.equal(coef, coef2) and torch.equal(dst, dst2)
+        # and so does the launch shape the autotuner picks for this batch (XCD
+        # order, cached pixel accesses)
+        coef2.zero_()
+        dst2.zero_()
+        tune = dict(waves_per_group=1, groups_per_cu=4096, tile_waves=1, xcd_remap=1, pixel_cache=1)
+        p2 = tdct.tdct_batch_plan(d2, qs, tune=tune)
+        try:
+            tdct.tdct_batch_run(p2)
+            sync()
+        finally:
+            tdct.tdct_plan_free(p2)
         assert torch.equal(coef, coef2) and torch.equal(dst, dst2)
     finally:
         tdct.tdct_plan_free(plan)
