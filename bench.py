@@ -413,7 +413,8 @@ def fused_leg(tdct, torch, W, stream, reps=10, tune=None):
         roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "T VALU lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "valu_lane_ops_per_px": round(lane_ops / px, 3)}
-    return {"kernel": "batch_kernel<32> (round trip, coefficients kept in registers)", "tune": tune,
+    return {"kernel": "batch_kernel<32, %s> (round trip, coefficients kept in registers)"
+            % ("true" if tune.get("pixel_cache") else "false"), "tune": tune,
             "ms": round(ms, 4), "gpx_s": round(px / (ms / 1e3) / 1e9, 1),
             "gbs": round(2 * px / (ms / 1e3) / 1e9, 1), "bytes_per_px": 2, "roofline": roof}
 
@@ -444,7 +445,8 @@ def forward_leg(tdct, torch, W, stream, reps=10):
         tdct.tdct_plan_free(plan)
     del Y
     gbs = 5 * W["pixels"] / (ms / 1e3) / 1e9
-    return {"kernel": "batch_kernel<16> (int32 forward)", "tune": tune, "ms": round(ms, 4),
+    return {"kernel": "batch_kernel<16, %s> (int32 forward)" % ("true" if tune.get("pixel_cache") else "false"),
+            "tune": tune, "ms": round(ms, 4),
             "gpx_s": round(W["pixels"] / (ms / 1e3) / 1e9, 1), "gbs": round(gbs, 1),
             "bytes_per_px": 5, "frac_of_8tbs": round(gbs / 8000.0, 4)}
 
