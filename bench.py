@@ -261,9 +261,27 @@ def latency_leg(tdct, torch, stream, side=512, reps=100):
     return out
 
 
+def graph_replay_ms(tdct, torch, plan, stream, warm=5, n=11):
+    """Median device time (ms) of one replay of the plan's graph: the graph
+    is captured and replayed `warm` times first, so that the clocks settle
+    after the idle gap of the capture (the first launches after such a gap
+    run up to 25 % slower), then each of `n` replays is timed with events on
+    the launch stream."""
+    for _ in range(1 + warm):
+        tdct.tdct_batch_graph(plan, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    ev[0].record(stream)
+    for k in range(n):
+        tdct.tdct_batch_graph(plan, stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    return sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(n))[n // 2]
+
+
 def batched_leg(tdct, torch, stream, n=10000, reps=5):
     """10,000 ragged images, encode + decode round trip with coefficients:
-    persistent launch (graph replay) vs one plain launch per image, and vs
+    persistent launch (graph replay median) vs one plain launch per image, and vs
     the same per-image launches captured in one hipGraph (no launch
     overhead: what remains is the cost of 10,000 small grids)."""
     import numpy as np
@@ -286,13 +304,7 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
     plan = tdct.tdct_batch_plan(descs, qs)
     try:
         tune = tdct.tdct_autotune(plan, stream, reps=2)
-        tdct.tdct_batch_graph(plan, stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            tdct.tdct_batch_graph(plan, stream)
-        torch.cuda.synchronize()
-        graph_s = (time.perf_counter() - t0) / reps
+        graph_s = graph_replay_ms(tdct, torch, plan, stream) / 1e3
         tdct.tdct_run_per_image(descs, qs, stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -487,13 +499,7 @@ def video_leg(tdct, torch, stream, frames=256, reps=5):
     plan = tdct.tdct_batch_plan(descs, qtabs)
     try:
         tune = tdct.tdct_autotune(plan, stream, reps=2)
-        tdct.tdct_batch_graph(plan, stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            tdct.tdct_batch_graph(plan, stream)
-        torch.cuda.synchronize()
-        graph_s = (time.perf_counter() - t0) / reps
+        graph_s = graph_replay_ms(tdct, torch, plan, stream) / 1e3
         tdct.tdct_run_per_image(descs, qtabs, stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -193,8 +193,9 @@ int tdct_batch_graph(tdct_plan* plan, void* stream);
 
 /* Times candidate launch shapes on the plan (reps launches each, after one
  * warm-up), then times the four fastest again in turn over max(5, reps)
- * rounds, keeps the one with the lowest median in the plan and returns it
- * in *best. Outputs are overwritten with the same bytes by every candidate. */
+ * rounds or more (up to 25, about 0.2 s of launches), keeps the one with the
+ * lowest median in the plan and returns it in *best. Outputs are overwritten
+ * with the same bytes by every candidate. */
 int tdct_autotune(tdct_plan* plan, void* stream, int32_t reps, tdct_tune* best);
 
 int tdct_plan_info_get(const tdct_plan* plan, tdct_plan_info* out);

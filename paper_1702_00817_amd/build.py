@@ -47,7 +47,9 @@ def build_lib(verbose: bool = False) -> str:
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(bdir, src + ".o")
-        lang = ["-x", "hip"] + DEVICE if src.endswith(".hip") else ["-D__HIP_PLATFORM_AMD__"]
+        # hipcc compiles .cpp files as HIP too: every source names the target,
+        # so no code object for any other GPU is made
+        lang = ["-x", "hip"] + DEVICE
         _run([HIPCC] + COMMON + lang + PER_SOURCE.get(src, []) + ["-c", path, "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()

@@ -324,6 +324,7 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
         size_t k = 0;
         tdct_tune winner = saved;
         int st = TDCT_OK;
+        int rounds = 0;
         // Stage 1: every launch shape (persistent grids of 1..16 resident waves
         // per CU, and a full grid where every wave takes tile_waves tiles and
         // exits; tiles in launch order or one contiguous range per XCD;
@@ -357,11 +358,19 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
                         }
         // Stage 2: the four fastest again, round-robin over several rounds, so
         // that a drift of the clocks between candidates cannot pick the winner.
+        // Launch times scatter by a few per cent while the best shapes differ
+        // by about as much, so the rounds fill about 0.2 s of launches (at
+        // least max(5, reps), at most 25).
         std::sort(cands.begin(), cands.end(),
                   [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
         k = std::min<size_t>(4, cands.size());
         finals.assign(k, {});
-        for (int r = 0; r < std::max(5, reps); ++r)
+        rounds = std::max(5, reps);
+        if (k) {
+            const double per_round_ms = (double)k * std::max(cands[0].ms, 1e-3f);
+            rounds = std::max(rounds, std::min(25, (int)(200.0 / per_round_ms)));
+        }
+        for (int r = 0; r < rounds; ++r)
             for (size_t c = 0; c < k; ++c) {
                 float m = 0;
                 if ((st = time_one(cands[c].t, &m))) goto done;
