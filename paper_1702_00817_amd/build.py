@@ -62,7 +62,7 @@ def build_lib(verbose: bool = False) -> str:
 def build_hostcheck(verbose: bool = False) -> str:
     """Host-only test helper built from the library's device header."""
     tmp = HOSTCHECK_LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC] + COMMON + ["-shared", "-o", tmp, HOSTCHECK_SRC], verbose)
+    _run([HIPCC] + COMMON + ["-x", "hip"] + DEVICE + ["-shared", "-o", tmp, HOSTCHECK_SRC], verbose)
     os.replace(tmp, HOSTCHECK_LIB)
     return HOSTCHECK_LIB
 
