@@ -157,6 +157,7 @@ inline float quant_recip(int Q, int s, bool kept) {
 struct QConst {
     float r[64];
     int32_t Q[64];
+    float qs[64];  // Q / 64 in fp32: multipliers of the round trips' fp32 decoder half
 };
 
 enum : int32_t { OP_ENCODE = 0, OP_DECODE = 1, OP_ROUNDTRIP = 2, OP_ENCODE_I8ZZ = 3, OP_FORWARD = 4,

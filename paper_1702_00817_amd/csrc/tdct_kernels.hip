@@ -156,6 +156,7 @@ void make_qconst(const tdct_qtable* Q, int keep, QConst* out) {
             const int q = Q ? Q->q[k] : 1;
             out->r[k] = quant_recip(q, kShift(i, j), kZigzag.rank[k] < keep);
             out->Q[k] = q;
+            out->qs[k] = (float)q / 64.0f;  // exact: q < 2^12
         }
 }
 

@@ -252,6 +252,52 @@ __device__ __forceinline__ void reconstruct(int (&W)[64], uint32_t (&px)[8][2]) 
     }
 }
 
+// The decoder half of a round trip, in fp32. There q comes from the encoder,
+// so |q Q| <= |W| + Q / 2 < 10240 and W'' = q Q / 64 is a multiple of 1/64 of
+// magnitude below 160. Every value of the inverse transform is a signed sum of
+// some of the 64 inputs plus the bias c = 128 + 1/128 folded into W''_00 (which
+// reaches every output, column 0 of T^t being all ones): a multiple of 1/128
+// below 10240 + 129 in magnitude, under 2^24 units of 1/128, so each fp32
+// addition is exact and the result is S / 64 + c exactly, S = T^t W' T.
+// With y = (S + 32) / 64 + 128, whose fraction f is a multiple of 1/64, the
+// result is z = y - 63/128 = floor(y) + (f - 63/128), and |f - 63/128| < 1/2:
+// rounding z to the nearest integer gives floor(y), never from a tie. The
+// hardware conversion to u8 rounds to nearest and saturates to [0, 255], so
+// one instruction per pixel yields clamp(floor((S + 32) / 64) + 128), packed.
+// (The general decoder keeps int32: an arbitrary int16 q times Q up to 4095
+// leaves fp32's exact range.)
+constexpr float kPixelBiasF = 128.0f + 1.0f / 128.0f;
+
+__device__ __forceinline__ void reconstruct_f(float (&W)[64], uint32_t (&px)[8][2]) {
+    W[0] += kPixelBiasF;
+    inv8x8(W);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float* w = &W[8 * r + 4 * h];
+            uint32_t p = __builtin_amdgcn_cvt_pk_u8_f32(w[0], 0u, 0u);
+            p = __builtin_amdgcn_cvt_pk_u8_f32(w[1], 1u, p);
+            p = __builtin_amdgcn_cvt_pk_u8_f32(w[2], 2u, p);
+            px[r][h] = __builtin_amdgcn_cvt_pk_u8_f32(w[3], 3u, p);
+        }
+    }
+}
+
+// Round-trip decoder half from int16 coefficients the encoder just made (32
+// dwords, natural order, two per dword): W'' = q (Q / 64), exact in fp32.
+template <class QC>
+__device__ __forceinline__ void decode_block_rt(const uint32_t (&qp)[32], const QC& qc,
+                                                uint32_t (&px)[8][2]) {
+    float W[64];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        W[2 * k] = (float)(int)(short)(qp[k] & 0xffffu) * qc.qs[2 * k];
+        W[2 * k + 1] = (float)((int)qp[k] >> 16) * qc.qs[2 * k + 1];
+    }
+    reconstruct_f(W, px);
+}
+
 // Dequantise + inverse transform of one block whose int16 coefficients sit in
 // 32 dwords (natural order, two per dword), producing 8 rows of 8 pixels.
 template <class QC>
@@ -390,27 +436,26 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
         stage_out<4>(wl, ma, 4 * na, out, lane);
         if (nb) stage_out<4>(wl, mb, 4 * nb, out + 256, lane);
     } else if constexpr (OP == OP_ROUNDTRIP_NC) {
-        // Encode and decode without storing coefficients. The rounding
-        // float's low 24 bits are 0x400000 + q (|q| < 2^22), so one 24-bit
-        // multiply-add gives W' = q Q directly: (0x400000 + q) Q - (Q << 22),
-        // exact modulo 2^32 and |q Q| < 2^31.
+        // Encode and decode without storing coefficients. The rounding float
+        // t is M + q exactly (an integer in [2^23, 2^24)), so t - M is q as an
+        // fp32 value and (t - M) (Q / 64) is the fp32 decoder's input.
         uint32_t px[8][2];
         if (va) {
-            int W[64];
+            float W[64];
 #pragma unroll
             for (int k = 0; k < 64; ++k)
-                W[k] = (int)(__umul24(quant_bits(v[k].x, qc.r[k]), (uint32_t)qc.Q[k]) -
-                             ((uint32_t)qc.Q[k] << 22));
-            reconstruct(W, px);
+                W[k] = (__builtin_bit_cast(float, quant_bits(v[k].x, qc.r[k])) - kRoundMagic) *
+                       qc.qs[k];
+            reconstruct_f(W, px);
             store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
         }
         if (vb) {
-            int W[64];
+            float W[64];
 #pragma unroll
             for (int k = 0; k < 64; ++k)
-                W[k] = (int)(__umul24(quant_bits(v[k].y, qc.r[k]), (uint32_t)qc.Q[k]) -
-                             ((uint32_t)qc.Q[k] << 22));
-            reconstruct(W, px);
+                W[k] = (__builtin_bit_cast(float, quant_bits(v[k].y, qc.r[k])) - kRoundMagic) *
+                       qc.qs[k];
+            reconstruct_f(W, px);
             store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
         }
     } else {
@@ -438,11 +483,11 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
         if constexpr (OP == OP_ROUNDTRIP) {
             uint32_t px[8][2];
             if (va) {
-                decode_block(qa, qc, px);
+                decode_block_rt(qa, qc, px);
                 store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
             }
             if (vb) {
-                decode_block(qb, qc, px);
+                decode_block_rt(qb, qc, px);
                 store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
             }
         }
