@@ -143,6 +143,12 @@ __host__ __device__ __forceinline__ int quant_int(int y, float r) {
     return (int)(quant_bits(y, r) - kRoundMagicBits);
 }
 
+// Bias of the round trips' fp32 decoder half, added to W''_00 = q Q / 64 at
+// position (0, 0): every output becomes S / 64 + 128 + 1/128, which rounds to
+// nearest as floor((S + 32) / 64) + 128 (the fraction of S / 64 is a multiple
+// of 1/64, so the value is never a tie).
+constexpr float kPixelBiasF = 128.0f + 1.0f / 128.0f;
+
 // Host-side constant for position (i, j): r as above, or 0 if masked.
 inline float quant_recip(int Q, int s, bool kept) {
     if (!kept) return 0.0f;

@@ -255,18 +255,19 @@ __device__ __forceinline__ void reconstruct(int (&W)[64], uint32_t (&px)[8][2]) 
 // The decoder half of a round trip, in fp32. There q comes from the encoder,
 // so |q Q| <= |W| + Q / 2 < 10240 and W'' = q Q / 64 is a multiple of 1/64 of
 // magnitude below 160. Every value of the inverse transform is a signed sum of
-// some of the 64 inputs plus the bias c = 128 + 1/128 folded into W''_00 (which
-// reaches every output, column 0 of T^t being all ones): a multiple of 1/128
-// below 10240 + 129 in magnitude, under 2^24 units of 1/128, so each fp32
-// addition is exact and the result is S / 64 + c exactly, S = T^t W' T.
+// at most 16 of the 64 inputs (each column of T has four nonzeros) plus the
+// bias c = 128 + 1/128 folded into W''_00 (which reaches every output, column 0
+// of T^t being all ones): a multiple of 1/128 below 2560 + 129 in magnitude,
+// far under 2^24 units of 1/128, so each fp32 addition (and each multiply
+// folded into one as an FMA) is exact and the result is S / 64 + c exactly,
+// S = T^t W' T.
 // With y = (S + 32) / 64 + 128, whose fraction f is a multiple of 1/64, the
 // result is z = y - 63/128 = floor(y) + (f - 63/128), and |f - 63/128| < 1/2:
 // rounding z to the nearest integer gives floor(y), never from a tie. The
 // hardware conversion to u8 rounds to nearest and saturates to [0, 255], so
 // one instruction per pixel yields clamp(floor((S + 32) / 64) + 128), packed.
 // (The general decoder keeps int32: an arbitrary int16 q times Q up to 4095
-// leaves fp32's exact range.)
-constexpr float kPixelBiasF = 128.0f + 1.0f / 128.0f;
+// leaves fp32's exact range.) The bias kPixelBiasF is in tdct_device.hpp.
 
 __device__ __forceinline__ void reconstruct_f(float (&W)[64], uint32_t (&px)[8][2]) {
     W[0] += kPixelBiasF;

@@ -105,4 +105,23 @@ void hc_xcd_order(uint32_t n, uint32_t* out) {
     for (uint32_t b = 0; b < n; ++b) out[b] = tdct::xcd_order(b, n);
 }
 
+// The round trips' fp32 decoder half on the host, for n blocks of W' = q Q
+// (int32, natural order): W'' = W' / 64 with the pixel bias at (0, 0), the
+// library's inverse butterflies in fp32, the values before the conversion to
+// u8 (out), and the pixels that conversion makes -- round to nearest, ties to
+// even, saturated to [0, 255] (pix).
+void hc_inverse_f32(const int32_t* wq, int64_t n, float* out, uint8_t* pix) {
+    for (int64_t b = 0; b < n; ++b) {
+        float W[64];
+        for (int k = 0; k < 64; ++k) W[k] = (float)wq[64 * b + k] * (1.0f / 64.0f);
+        W[0] += tdct::kPixelBiasF;
+        tdct::inv8x8(W);
+        for (int k = 0; k < 64; ++k) {
+            out[64 * b + k] = W[k];
+            const float r = __builtin_nearbyintf(W[k]);
+            pix[64 * b + k] = (uint8_t)(r < 0.0f ? 0.0f : r > 255.0f ? 255.0f : r);
+        }
+    }
+}
+
 }  // extern "C"

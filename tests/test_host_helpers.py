@@ -33,6 +33,7 @@ def hc():
     L.hc_quant.argtypes = [ctypes.c_int32] * 4 + [P]
     L.hc_quant_lanes.argtypes = [ctypes.c_int32] * 4 + [P, P]
     L.hc_xcd_order.argtypes = [ctypes.c_uint32, P]
+    L.hc_inverse_f32.argtypes = [P, ctypes.c_int64, P, P]
     return L
 
 
@@ -156,3 +157,36 @@ def test_xcd_order_is_a_bijection_with_one_contiguous_range_per_xcd(hc, n):
         places = out[x::8]  # XCD x's workgroups in launch order
         assert np.array_equal(places, np.arange(nxt, nxt + places.size, dtype=np.uint32))
         nxt += places.size
+
+
+def test_fp32_round_trip_decoder_is_exact(hc, oracle_mod):
+    """The round trips decode in fp32. With q from the encoder |q Q| < 10240;
+    over that whole range (random blocks, plus for every output the block
+    whose signs drive that output to its extreme) the fp32 inverse of
+    q Q / 64 with the pixel bias equals S / 64 + 128 + 1/128 exactly (S from
+    the oracle's integer inverse), and rounding it to nearest with
+    saturation gives the integer decoder's clamp(floor((S + 32) / 64) + 128)."""
+    T = oracle_mod.T().astype(np.int64)
+    rng = np.random.default_rng(61)
+    blocks = [rng.integers(-10240, 10241, size=(4000, 64)),
+              rng.integers(-300, 301, size=(4000, 64)),        # near the clamps
+              np.full((1, 64), 10240), np.full((1, 64), -10240)]
+    ext = []
+    for r in range(8):
+        for c in range(8):
+            sg = np.sign(np.outer(T[:, r], T[:, c]))           # sign of T_ir T_jc
+            ext += [10240 * sg, -10240 * sg]
+    blocks.append(np.array(ext).reshape(-1, 64))
+    wq = np.ascontiguousarray(np.concatenate(blocks).astype(np.int32))
+    n = wq.shape[0]
+    out = np.zeros((n, 64), np.float32)
+    pix = np.zeros((n, 64), np.uint8)
+    hc.hc_inverse_f32(wq.ctypes.data, n, out.ctypes.data, pix.ctypes.data)
+    S = np.stack([oracle_mod.inverse_block(wq[b].reshape(8, 8)).reshape(64) for b in range(n)])
+    # the extreme blocks reach the largest |S| there is: 10240 times the
+    # number of nonzero T_ir T_jc, maximised over the output (r, c)
+    nz = (T != 0).sum(axis=0)
+    assert np.abs(S).max() == 10240 * int(nz.max()) ** 2
+    np.testing.assert_array_equal(out.astype(np.float64), S / 64.0 + 128.0 + 1.0 / 128.0)
+    want = np.clip(np.floor_divide(S + 32, 64) + 128, 0, 255)
+    np.testing.assert_array_equal(pix, want)
