@@ -393,9 +393,10 @@ def load_valu(name: str):
 
 def fused_leg(tdct, torch, W, stream, reps=10, tune=None):
     """Encode + decode in one pass with no coefficients in HBM (2 B/px) on the
-    same 64 x 4096^2 batch. Bound by VALU issue, not HBM: its roofline is the
-    counted VALU instructions per launch over the launch time, against the
-    part's VALU issue peak."""
+    same 64 x 4096^2 batch. It runs near two bounds, HBM and VALU issue; its
+    roofline gives both (the counted VALU instructions per launch over the
+    launch time against the part's VALU issue peak, and 2 B/px against
+    8 TB/s), the nearer one on top."""
     n = len(W["sizes"])
     side = W["sizes"][0][0]
     base = W["src"].data_ptr()
