@@ -189,6 +189,20 @@ def test_constant_planes_and_saturating_patterns(tdct, oracle_mod):
             q = _encode(tdct, im, Q)
             assert np.array_equal(q, O.quantise(im, Q))
             assert np.array_equal(_decode(tdct, q, Q, w, h), O.inverse(q, Q, w, h))
+            # the round trips decode in fp32 and saturate in the u8 conversion:
+            # these patterns overshoot both ends of [0, 255]
+            _, sp = plane_dev(im)
+            for keep in (64, 3):
+                q_ref, rec_ref = O.roundtrip(im, Q, keep)
+                for with_q in (True, False):
+                    qo = Guarded(w * h * 2) if with_q else None
+                    out = Guarded(w * h)
+                    tdct.tdct_roundtrip(sp, w, w, h, Q, keep, qo.ptr if qo else None, out.ptr, w)
+                    sync()
+                    assert out.guards_intact() and np.array_equal(out.host().reshape(h, w), rec_ref)
+                    if qo:
+                        assert qo.guards_intact()
+                        assert np.array_equal(qo.host().view(np.int16).reshape(-1, 64), q_ref)
     Y = O.forward(img).astype(np.int64)
     W = Y * oracle_mod.wscale().reshape(1, 64)
     assert Y[:, 0].min() == -8192 and Y[:, 0].max() == 8128  # the DC extremes are reached
