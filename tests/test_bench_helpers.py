@@ -15,3 +15,19 @@ def test_dct_reference_is_orthonormal_dct2():
     x = np.arange(8, dtype=float)
     y = C @ x
     assert np.allclose(y[2::2], 0, atol=1e-12)
+
+
+def test_launch_shape_parsing():
+    """--tune / --fused-tune accept 3 to 5 fields; missing ones are 0."""
+    assert bench.parse_tune("4,1,2") == dict(waves_per_group=4, groups_per_cu=1, tile_waves=2,
+                                             xcd_remap=0, pixel_cache=0)
+    assert bench.parse_tune("2,4096,1,1") == dict(waves_per_group=2, groups_per_cu=4096, tile_waves=1,
+                                                  xcd_remap=1, pixel_cache=0)
+    assert bench.parse_tune("8,1,1,0,1") == dict(waves_per_group=8, groups_per_cu=1, tile_waves=1,
+                                                 xcd_remap=0, pixel_cache=1)
+    for bad in ("4,1", "1,2,3,4,5,6"):
+        try:
+            bench.parse_tune(bad)
+        except SystemExit:
+            continue
+        raise AssertionError(bad)
