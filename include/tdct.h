@@ -179,7 +179,12 @@ typedef struct tdct_plan tdct_plan;
  * blocks per image and the image-uniform tile list, and uploads both with
  * the per-table quantiser constants to device tables the plan owns.
  * Image descriptors and tables are copied; device buffers they name must
- * stay valid while the plan is run. */
+ * stay valid while the plan is run. A plan may run many times (graph
+ * replays, the autotuner's candidates), so no image may write bytes that
+ * any image of the plan reads: TDCT_EINVAL if the span an image reads (its
+ * plane rows from src to the last row's end, or a decoder's coefficient run)
+ * meets the span any image writes (an in-place round trip, or a decode of
+ * coefficients another image of the plan encodes). */
 int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
                     int32_t nq, const tdct_tune* tune_or_null, tdct_plan** out);
 
@@ -195,7 +200,8 @@ int tdct_batch_graph(tdct_plan* plan, void* stream);
  * warm-up), then times the four fastest again in turn over max(5, reps)
  * rounds or more (up to 25, about 0.2 s of launches), keeps the one with the
  * lowest median in the plan and returns it in *best. Outputs are overwritten
- * with the same bytes by every candidate. */
+ * with the same bytes by every candidate (a plan's outputs never overlap its
+ * inputs, see tdct_batch_plan). */
 int tdct_autotune(tdct_plan* plan, void* stream, int32_t reps, tdct_tune* best);
 
 int tdct_plan_info_get(const tdct_plan* plan, tdct_plan_info* out);
@@ -223,7 +229,11 @@ typedef struct {
     int32_t fake_device_us; /* > 0: no GPU at all -- outputs live in host memory and a
                                batch "completes" this many microseconds after launch
                                (exercises admission and batching on a CPU) */
-    int32_t fake_fail_every; /* fake device only: every n-th batch fails (0 = never) */
+    int32_t fake_fail_every; /* fake device only: n > 0: every n-th batch fails when it
+                                completes; n < 0: every |n|-th batch fails partway through
+                                its launch, after its work was queued (0 = never). A batch
+                                whose launch fails gives its memory back only once the work
+                                it queued has drained */
     /* Resident mode (resident = 1): no launch per batch. Requests go into a
      * queue in host-coherent pinned memory that a resident kernel polls; its
      * front wave copies each request to the device and cuts it into work

@@ -104,6 +104,63 @@ int validate_image(const tdct_image_desc& im, int32_t nq) {
     return TDCT_OK;
 }
 
+// Byte ranges an image reads and writes (the span of its plane rows or of its
+// coefficient run).
+struct Span {
+    uintptr_t lo, hi;
+};
+
+Span plane_span(const void* p, int64_t stride, int32_t w, int32_t h) {
+    const uintptr_t a = (uintptr_t)p;
+    return {a, a + (uintptr_t)((int64_t)(h - 1) * stride + w)};
+}
+
+Span coef_span(const void* p, int64_t nblk, int64_t bytes_per_coef) {
+    const uintptr_t a = (uintptr_t)p;
+    return {a, a + (uintptr_t)(nblk * 64 * bytes_per_coef)};
+}
+
+// A plan is run again and again (graph replays, the autotuner's candidates),
+// so no image may write bytes that an image of the plan reads: an in-place
+// round trip, or a decode of coefficients another image encodes, would
+// compound over the runs. TDCT_EINVAL if any input span meets any output span.
+int check_no_overlap(const tdct_image_desc* imgs, int32_t n) {
+    std::vector<Span> in, out;
+    in.reserve((size_t)n);
+    out.reserve((size_t)n + 8);
+    for (int32_t i = 0; i < n; ++i) {
+        const tdct_image_desc& im = imgs[i];
+        const int64_t nblk = (int64_t)(im.w / 8) * (im.h / 8);
+        switch (im.op) {
+            case TDCT_OP_DECODE:
+                in.push_back(coef_span(im.coef, nblk, 2));
+                out.push_back(plane_span(im.dst, im.dst_stride, im.w, im.h));
+                break;
+            case TDCT_OP_ROUNDTRIP:
+                in.push_back(plane_span(im.src, im.src_stride, im.w, im.h));
+                out.push_back(plane_span(im.dst, im.dst_stride, im.w, im.h));
+                if (im.coef) out.push_back(coef_span(im.coef, nblk, 2));
+                break;
+            default:
+                in.push_back(plane_span(im.src, im.src_stride, im.w, im.h));
+                out.push_back(coef_span(im.coef, nblk,
+                                        im.op == TDCT_OP_ENCODE ? 2 : im.op == TDCT_OP_FORWARD ? 4 : 1));
+                break;
+        }
+    }
+    std::sort(out.begin(), out.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+    // reach[k]: the furthest end among the first k + 1 output spans
+    std::vector<uintptr_t> reach(out.size());
+    for (size_t k = 0; k < out.size(); ++k) reach[k] = std::max(out[k].hi, k ? reach[k - 1] : 0);
+    for (const Span& s : in) {
+        const size_t k = (size_t)(std::lower_bound(out.begin(), out.end(), s.hi,
+                                                   [](const Span& a, uintptr_t v) { return a.lo < v; }) -
+                                  out.begin());
+        if (k && reach[k - 1] > s.lo) return TDCT_EINVAL;
+    }
+    return TDCT_OK;
+}
+
 void free_graph(tdct_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -132,6 +189,7 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
             if ((st = validate_q(&qtabs[k]))) return st;
         for (int32_t i = 0; i < n; ++i)
             if ((st = validate_image(imgs[i], nq))) return st;
+        if ((st = check_no_overlap(imgs, n))) return st;
 
         // freed with everything it holds on any early return
         std::unique_ptr<tdct_plan, void (*)(tdct_plan*)> p(new (std::nothrow) tdct_plan(),

@@ -119,7 +119,8 @@ struct Slot {
     bool launching = false;  // claimed, launch calls in progress without the lock
     double launched_us = 0;
     double fake_done_us = 0;
-    bool fake_fail = false;
+    bool fake_fail = false;         // fake device: the batch fails when it completes
+    bool fake_launch_fail = false;  // fake device: the launch fails after queuing its work
     std::vector<uint64_t> tickets;
     void* dev = nullptr;  // tiles | descriptors | constants
     size_t dev_cap = 0;
@@ -299,7 +300,11 @@ int stage_input(const BatchItem& it, hipStream_t st) {
 
 // Builds tables for the batch and launches it on the slot. No lock held.
 int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>& items) {
-    if (s->fake) return TDCT_OK;
+    if (s->fake) {
+        if (!sl.fake_launch_fail) return TDCT_OK;
+        set_error_text("fake device: launch failed after its work was queued");
+        return TDCT_EDEVICE;
+    }
     const int n = (int)items.size();
     if (!s->cfg.batching || n == 1) {
         // Plain launches with everything in the kernel arguments: the
@@ -491,8 +496,10 @@ double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
         s->batch_reqs += (int64_t)items.size();
         sl.launched_us = now;
         if (s->fake) {
+            const int every = s->cfg.fake_fail_every;
             sl.fake_done_us = s->now_us() + s->cfg.fake_device_us;
-            sl.fake_fail = s->cfg.fake_fail_every > 0 && (s->batches % s->cfg.fake_fail_every) == 0;
+            sl.fake_fail = every > 0 && (s->batches % every) == 0;
+            sl.fake_launch_fail = every < 0 && (s->batches % -(int64_t)every) == 0;
         }
         sl.launching = true;
         lk.unlock();
@@ -503,10 +510,29 @@ double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
             set_error_text("host memory allocation for a batch failed");
             st = TDCT_ENOMEM;
         }
+        if (st) {
+            // Work the failed launch had already queued on the slot's stream
+            // (input copies, the table upload from the pinned staging buffer,
+            // the kernel) may still be running: the batch's arena bytes, the
+            // staging buffer and the slot are handed out again only once the
+            // stream has drained.
+            if (s->fake) {
+                const double left = sl.fake_done_us - s->now_us();
+                if (left > 0)
+                    std::this_thread::sleep_for(std::chrono::microseconds((int64_t)left + 1));
+            } else {
+                (void)hipStreamSynchronize(sl.stream);
+            }
+        }
         lk.lock();
         sl.launching = false;
         if (st) {
             memcpy(s->err, tdct_last_error(), sizeof(s->err) - 1);
+            // the fake device's queued work must have ended before the
+            // batch's memory goes back
+            if (s->fake && s->now_us() < sl.fake_done_us)
+                snprintf(s->err, sizeof(s->err), "fake device: a failed batch's memory was released "
+                                                  "while its queued work ran");
             const double t_now = s->now_us();
             const int bs = (int)sl.tickets.size();
             for (uint64_t t : sl.tickets) finish_request(s, t, st, bs, t_now);

@@ -75,6 +75,37 @@ def test_argument_errors_need_no_device(tdct):
         assert L.tdct_batch_plan((tdct.tdct_image_desc * 1)(d), 1, qa, 1, r(t), r(h)) == tdct.TDCT_EINVAL
 
 
+def test_plans_refuse_outputs_over_inputs(tdct):
+    """A plan runs many times (graph replays, autotuning), so an image may not
+    write bytes any image of the plan reads: an in-place round trip, a decode
+    of coefficients the same plan encodes, or an output plane reaching into
+    another image's rows are refused before any device is touched."""
+    L = tdct.lib()
+    qa = (tdct.tdct_qtable * 1)(tdct.qtable(np.ones(64)))
+    h = ctypes.c_void_p()
+
+    def plan(*descs):
+        arr = (tdct.tdct_image_desc * len(descs))(*descs)
+        return L.tdct_batch_plan(arr, len(descs), qa, 1, None, ctypes.byref(h))
+
+    a, b, c = 1 << 32, 2 << 32, 3 << 32
+    rt = tdct.image_desc(tdct.OP_ROUNDTRIP, 64, 64, src=a, src_stride=64, dst=a, dst_stride=64)
+    assert plan(rt) == tdct.TDCT_EINVAL
+    enc = tdct.image_desc(tdct.OP_ENCODE, 64, 64, src=a, src_stride=64, coef=b)
+    dec = tdct.image_desc(tdct.OP_DECODE, 64, 64, coef=b + 128 * 63, dst=c, dst_stride=64)
+    assert plan(enc, dec) == tdct.TDCT_EINVAL
+    # the last row of a strided plane ends at (h - 1) * stride + w
+    enc2 = tdct.image_desc(tdct.OP_ENCODE, 64, 64, src=c + 63 * 100 + 63, src_stride=100, coef=b)
+    dec2 = tdct.image_desc(tdct.OP_DECODE, 64, 64, coef=a, dst=c, dst_stride=100)
+    assert plan(enc2, dec2) == tdct.TDCT_EINVAL
+    # adjacent spans do not meet: validation passes, and the missing device
+    # (or a real one) decides the rest
+    dec3 = tdct.image_desc(tdct.OP_DECODE, 64, 64, coef=b + 128 * 64, dst=c, dst_stride=64)
+    assert plan(enc, dec3) != tdct.TDCT_EINVAL
+    if h.value:
+        L.tdct_plan_free(h)
+
+
 # ---- server logic on the fake device ----------------------------------------
 
 def test_server_tune_is_validated(tdct):
@@ -189,6 +220,30 @@ def test_fake_server_failed_batches_do_not_stop_service(tdct):
         assert st["failed"] == 3 and st["completed"] == 6
         # failed requests gave their memory back
         for t, stt in zip(tickets, status):
+            tdct.tdct_server_release(s, t)
+        assert tdct.tdct_server_stats(s)["arena_bytes_in_use"] == 0
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
+def test_fake_server_launch_failure_waits_for_queued_work(tdct):
+    """A batch whose launch fails after part of its work was queued on the
+    slot's stream gives its arena bytes and its slot back only once that work
+    has drained (the fake device checks it), and the server goes on."""
+    us = 3000
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 22, streams=1, max_batch=1, fake_device_us=us,
+                                                fake_fail_every=-2))
+    try:
+        tickets = [tdct.tdct_server_submit(s, _req(tdct, tdct.OP_DECODE, 32, 32)) for _ in range(6)]
+        tdct.tdct_server_drain(s)
+        res = [tdct.tdct_server_poll(s, t) for t in tickets]
+        status = [r.status for r in res]
+        assert status.count(tdct.TDCT_EDEVICE) == 3 and status.count(tdct.TDCT_OK) == 3
+        for r in res:  # failed or not, each request waited for its queued work
+            assert r.done_us - r.submit_us >= us
+        assert "released while" not in tdct.tdct_server_last_error(s)
+        assert "after its work was queued" in tdct.tdct_server_last_error(s)
+        for t in tickets:
             tdct.tdct_server_release(s, t)
         assert tdct.tdct_server_stats(s)["arena_bytes_in_use"] == 0
     finally:

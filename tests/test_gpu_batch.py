@@ -119,6 +119,7 @@ def test_tile_size_and_default_shape_of_plans(tdct):
     import torch
     simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
     fake = 0x100000
+    out = 1 << 40  # outputs apart from inputs: a plan refuses overlapping ones
     q = [np.ones(64, np.uint16)]
 
     def tiles(descs):
@@ -132,13 +133,13 @@ def test_tile_size_and_default_shape_of_plans(tdct):
         return info["tiles"]
 
     def enc(side):
-        return tdct.image_desc(tdct.OP_ENCODE, side, side, src=fake, src_stride=side, coef=fake)
+        return tdct.image_desc(tdct.OP_ENCODE, side, side, src=fake, src_stride=side, coef=out)
 
     def dec(side):
-        return tdct.image_desc(tdct.OP_DECODE, side, side, coef=fake, dst=fake, dst_stride=side)
+        return tdct.image_desc(tdct.OP_DECODE, side, side, coef=fake, dst=out, dst_stride=side)
 
     def fwd(side):
-        return tdct.image_desc(tdct.OP_FORWARD, side, side, src=fake, src_stride=side, coef=fake)
+        return tdct.image_desc(tdct.OP_FORWARD, side, side, src=fake, src_stride=side, coef=out)
 
     small = (512 // 8) ** 2  # 4096 blocks: 32 encoder tiles of 128
     assert small // 128 < simds
