@@ -73,9 +73,35 @@ int tdct::normalise_tune(const tdct_tune* in, tdct_tune* out) {
     return TDCT_OK;
 }
 
-namespace {
+// Image-uniform tiles from each image's block range, 64-block encoder-side
+// tiles when the batch is too small to fill the device.
+int64_t tdct::plan_tiles(const ImgDesc* imgs, int32_t n, int num_cus, Tile* out) {
+    int64_t full_tiles = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t tb = tile_blocks(imgs[i].op);
+        full_tiles += (imgs[i].nblk + tb - 1) / tb;
+    }
+    const bool small = shrink_tiles(full_tiles, num_cus);
+    int64_t k = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t nb = imgs[i].nblk;
+        const int tb = small ? kDecTileBlocks : tile_blocks(imgs[i].op);
+        if (!out) {
+            k += (nb + tb - 1) / tb;
+            continue;
+        }
+        for (int64_t f = 0; f < nb; f += tb, ++k) {
+            Tile& t = out[k];
+            t.img = (uint32_t)i;
+            t.first_lo = (uint32_t)f;
+            t.first_hi = (uint32_t)(f >> 32);
+            t.count = (uint32_t)std::min<int64_t>(tb, nb - f);
+        }
+    }
+    return k;
+}
 
-int validate_image(const tdct_image_desc& im, int32_t nq) {
+int tdct::validate_image(const tdct_image_desc& im, int32_t nq) {
     switch (im.op) {
         case TDCT_OP_ENCODE:
         case TDCT_OP_ROUNDTRIP:
@@ -104,11 +130,7 @@ int validate_image(const tdct_image_desc& im, int32_t nq) {
     return TDCT_OK;
 }
 
-// Byte ranges an image reads and writes (the span of its plane rows or of its
-// coefficient run).
-struct Span {
-    uintptr_t lo, hi;
-};
+namespace {
 
 Span plane_span(const void* p, int64_t stride, int32_t w, int32_t h) {
     const uintptr_t a = (uintptr_t)p;
@@ -120,46 +142,46 @@ Span coef_span(const void* p, int64_t nblk, int64_t bytes_per_coef) {
     return {a, a + (uintptr_t)(nblk * 64 * bytes_per_coef)};
 }
 
-// A plan is run again and again (graph replays, the autotuner's candidates),
-// so no image may write bytes that an image of the plan reads: an in-place
-// round trip, or a decode of coefficients another image encodes, would
-// compound over the runs. TDCT_EINVAL if any input span meets any output span.
-int check_no_overlap(const tdct_image_desc* imgs, int32_t n) {
-    std::vector<Span> in, out;
-    in.reserve((size_t)n);
-    out.reserve((size_t)n + 8);
+}  // namespace
+
+// Sorts the output spans by start and turns each end into the furthest end
+// among the spans up to it; an input span [lo, hi) then meets an output span
+// exactly when the last output starting before hi reaches past lo.
+int tdct::check_no_overlap(const tdct_image_desc* imgs, int32_t n, Span* in, Span* out) {
+    size_t nin = 0, nout = 0;
     for (int32_t i = 0; i < n; ++i) {
         const tdct_image_desc& im = imgs[i];
         const int64_t nblk = (int64_t)(im.w / 8) * (im.h / 8);
         switch (im.op) {
             case TDCT_OP_DECODE:
-                in.push_back(coef_span(im.coef, nblk, 2));
-                out.push_back(plane_span(im.dst, im.dst_stride, im.w, im.h));
+                in[nin++] = coef_span(im.coef, nblk, 2);
+                out[nout++] = plane_span(im.dst, im.dst_stride, im.w, im.h);
                 break;
             case TDCT_OP_ROUNDTRIP:
-                in.push_back(plane_span(im.src, im.src_stride, im.w, im.h));
-                out.push_back(plane_span(im.dst, im.dst_stride, im.w, im.h));
-                if (im.coef) out.push_back(coef_span(im.coef, nblk, 2));
+                in[nin++] = plane_span(im.src, im.src_stride, im.w, im.h);
+                out[nout++] = plane_span(im.dst, im.dst_stride, im.w, im.h);
+                if (im.coef) out[nout++] = coef_span(im.coef, nblk, 2);
                 break;
             default:
-                in.push_back(plane_span(im.src, im.src_stride, im.w, im.h));
-                out.push_back(coef_span(im.coef, nblk,
-                                        im.op == TDCT_OP_ENCODE ? 2 : im.op == TDCT_OP_FORWARD ? 4 : 1));
+                in[nin++] = plane_span(im.src, im.src_stride, im.w, im.h);
+                out[nout++] = coef_span(im.coef, nblk,
+                                        im.op == TDCT_OP_ENCODE ? 2 : im.op == TDCT_OP_FORWARD ? 4 : 1);
                 break;
         }
     }
-    std::sort(out.begin(), out.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
-    // reach[k]: the furthest end among the first k + 1 output spans
-    std::vector<uintptr_t> reach(out.size());
-    for (size_t k = 0; k < out.size(); ++k) reach[k] = std::max(out[k].hi, k ? reach[k - 1] : 0);
-    for (const Span& s : in) {
-        const size_t k = (size_t)(std::lower_bound(out.begin(), out.end(), s.hi,
+    std::sort(out, out + nout, [](const Span& a, const Span& b) { return a.lo < b.lo; });
+    for (size_t k = 1; k < nout; ++k) out[k].hi = std::max(out[k].hi, out[k - 1].hi);
+    for (size_t i = 0; i < nin; ++i) {
+        const Span& s = in[i];
+        const size_t k = (size_t)(std::lower_bound(out, out + nout, s.hi,
                                                    [](const Span& a, uintptr_t v) { return a.lo < v; }) -
-                                  out.begin());
-        if (k && reach[k - 1] > s.lo) return TDCT_EINVAL;
+                                  out);
+        if (k && out[k - 1].hi > s.lo) return TDCT_EINVAL;
     }
     return TDCT_OK;
 }
+
+namespace {
 
 void free_graph(tdct_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -189,7 +211,10 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
             if ((st = validate_q(&qtabs[k]))) return st;
         for (int32_t i = 0; i < n; ++i)
             if ((st = validate_image(imgs[i], nq))) return st;
-        if ((st = check_no_overlap(imgs, n))) return st;
+        {
+            std::vector<Span> in((size_t)n), out(2 * (size_t)n);
+            if ((st = check_no_overlap(imgs, n, in.data(), out.data()))) return st;
+        }
 
         // freed with everything it holds on any early return
         std::unique_ptr<tdct_plan, void (*)(tdct_plan*)> p(new (std::nothrow) tdct_plan(),
@@ -236,27 +261,10 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
             make_qconst(nullptr, 64, &qc);
             p->qcs.push_back(qc);
         }
-        // Image-uniform tiles from each image's block range; 64-block
-        // encoder-side tiles when the plan is too small to fill the device.
-        int64_t full_tiles = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            const int64_t tb = tile_blocks(p->imgs[i].op);
-            full_tiles += (p->blk_off[i + 1] - p->blk_off[i] + tb - 1) / tb;
-        }
-        const bool small = shrink_tiles(full_tiles, p->num_cus);
-        for (int32_t i = 0; i < n; ++i) {
-            const int64_t nb = p->blk_off[i + 1] - p->blk_off[i];
-            const int tb = small ? kDecTileBlocks : tile_blocks(p->imgs[i].op);
-            for (int64_t f = 0; f < nb; f += tb) {
-                Tile t;
-                t.img = (uint32_t)i;
-                t.first_lo = (uint32_t)f;
-                t.first_hi = (uint32_t)(f >> 32);
-                t.count = (uint32_t)std::min<int64_t>(tb, nb - f);
-                p->tiles.push_back(t);
-            }
-        }
-        if (p->tiles.size() >= 0xffffffffull) return TDCT_EINVAL;
+        const int64_t ntiles = plan_tiles(p->imgs.data(), n, p->num_cus, nullptr);
+        if (ntiles >= 0xffffffffll) return TDCT_EINVAL;
+        p->tiles.resize((size_t)ntiles);
+        plan_tiles(p->imgs.data(), n, p->num_cus, p->tiles.data());
         // One device allocation: tiles | descriptors | constants (256-B aligned parts).
         auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
         const size_t tb = up(p->tiles.size() * sizeof(Tile) + 16);

@@ -50,6 +50,22 @@ inline bool shrink_tiles(int64_t full_tiles, int num_cus) {
 // workgroup, a full grid, one tile per step); TDCT_EINVAL if a field is out
 // of range. `in` may be null (all defaults).
 int normalise_tune(const tdct_tune* in, tdct_tune* out);
+// The image-uniform tiles of a batch of filled descriptors (64-block
+// encoder-side tiles when shrink_tiles says so): returns their number and,
+// when `out` is not null, writes them there.
+int64_t plan_tiles(const ImgDesc* imgs, int32_t n, int num_cus, Tile* out);
+// Checks of one batch image against the plan's nq Q tables (status code).
+int validate_image(const tdct_image_desc& im, int32_t nq);
+// Byte span [lo, hi) an image reads or writes.
+struct Span {
+    uintptr_t lo, hi;
+};
+// A batch is run more than once (graph replays, autotuning) or in one launch
+// whose tiles run in any order, so no image may write bytes that any image
+// reads: TDCT_EINVAL if an input span (plane rows from src to the end of the
+// last row, or a decoder's coefficient run) meets an output span. `in` and
+// `out` are caller storage for n and 2 n spans (no allocation here).
+int check_no_overlap(const tdct_image_desc* imgs, int32_t n, Span* in, Span* out);
 // ops: bit i set when op i occurs in the tiles (selects the kernel instance).
 int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint32_t ntiles,
                  int ops, const tdct_tune& tune, int num_cus, hipStream_t stream);
