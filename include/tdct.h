@@ -117,9 +117,12 @@ int tdct_sse(const uint8_t* a, int64_t a_stride, const uint8_t* b, int64_t b_str
  *   WRITE dst[units]                        (16 B per unit)
  *   R1W2  src[units] -> dst[u] and dst[units + u] (48 B per unit; the encoder's 1:2 mix)
  *   R2W1  src[u] and src[units + u] -> dst[units] (48 B per unit; the decoder's 2:1 mix)
+ *   R1W3  src[units] -> dst[u], dst[units + u], dst[2 units + u] (64 B per unit; the
+ *         1:3 mix of a round trip that writes coefficients: 1 B in, 2 + 1 B out per pixel)
+ * COPY at 1:1 is also the mix of the int8 zigzag encoder (1 B in, 1 B out per sample).
  * Device pointers, 16-byte aligned, sized as above. */
 enum { TDCT_PROBE_COPY = 0, TDCT_PROBE_READ = 1, TDCT_PROBE_WRITE = 2, TDCT_PROBE_R1W2 = 3,
-       TDCT_PROBE_R2W1 = 4 };
+       TDCT_PROBE_R2W1 = 4, TDCT_PROBE_R1W3 = 5 };
 int tdct_stream_probe(int32_t kind, const void* src, void* dst, int64_t units, void* stream);
 
 const char* tdct_strerror(int status);
@@ -219,7 +222,11 @@ typedef struct {
     int32_t streams;       /* batches that may be in flight at once (1..16) */
     int32_t max_batch;     /* requests per batch, at most */
     int32_t max_wait_us;   /* a batch launches when a stream is free and either the
-                              queue holds max_batch requests or the oldest waited this long */
+                              queue holds max_batch requests or the oldest waited this long.
+                              0: no window; a free stream then takes its share of the
+                              admitted requests, ceil(admitted / streams) up to max_batch,
+                              so requests the free streams can take one by one launch
+                              alone and batches form under a backlog */
     int32_t batching;      /* 1 = continuous batching into the persistent kernel;
                               0 = one plain launch per request (comparison mode) */
     int64_t max_batch_px;  /* a batch stops growing once it holds this many pixels, so
@@ -323,11 +330,13 @@ void tdct_server_destroy(tdct_server* s);
  * starts (host clock); outputs are released as they complete unless
  * keep_outputs (then the caller releases the tickets, and TDCT_ENOMEM is
  * returned up front when all outputs together exceed the budget).
- * latency_us[k] receives submit -> completion; status[k] the final status.
- * Returns after every request has completed. */
+ * latency_us[k] receives submit -> completion; status[k] the final status;
+ * batch_size[k] the requests in the launch that served it (as in
+ * tdct_result). Output arrays may be NULL. Returns after every request has
+ * completed. */
 int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us,
                        int32_t n, int32_t keep_outputs, uint64_t* tickets_out,
-                       double* latency_us, int32_t* status);
+                       double* latency_us, int32_t* status, int32_t* batch_size);
 
 #ifdef __cplusplus
 }

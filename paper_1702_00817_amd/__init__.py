@@ -131,7 +131,7 @@ _SIG = {
     "tdct_server_stats": [_P, ctypes.POINTER(tdct_stats)],
     "tdct_server_replay": [_P, ctypes.POINTER(tdct_request), ctypes.POINTER(ctypes.c_double), _i32,
                            _i32, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double),
-                           ctypes.POINTER(ctypes.c_int32)],
+                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
 }
 for _name, _args in _SIG.items():
     getattr(_lib, _name).argtypes = _args
@@ -226,7 +226,7 @@ def tdct_sse(a, a_stride, b, b_stride, w, h, sse_dev, stream=None):
                          _stream(stream)), "tdct_sse")
 
 
-PROBE_COPY, PROBE_READ, PROBE_WRITE, PROBE_R1W2, PROBE_R2W1 = 0, 1, 2, 3, 4
+PROBE_COPY, PROBE_READ, PROBE_WRITE, PROBE_R1W2, PROBE_R2W1, PROBE_R1W3 = 0, 1, 2, 3, 4, 5
 
 
 def tdct_stream_probe(kind, src, dst, units, stream=None):
@@ -389,16 +389,28 @@ def tdct_server_destroy(server):
     _lib.tdct_server_destroy(server)
 
 
-def tdct_server_replay(server, reqs, arrival_us, keep_outputs=False):
-    """Returns (tickets, latency_us, status) as lists."""
+def request_array(n):
+    """A ctypes array of n requests (filled by the caller)."""
+    return (tdct_request * n)()
+
+
+def tdct_server_replay(server, reqs, arrival_us, keep_outputs=False, with_batch=False):
+    """Returns (tickets, latency_us, status) as lists, and the batch sizes as
+    a fourth list when with_batch. `reqs` is a sequence of tdct_request or an
+    array made by request_array."""
     n = len(reqs)
-    ra = (tdct_request * max(1, n))()
-    for i, r in enumerate(reqs):
-        ra[i] = r
+    if isinstance(reqs, ctypes.Array):
+        ra = reqs
+    else:
+        ra = request_array(n)
+        for i, r in enumerate(reqs):
+            ra[i] = r
     at = (ctypes.c_double * max(1, n))(*arrival_us)
     tk = (ctypes.c_uint64 * max(1, n))()
     lat = (ctypes.c_double * max(1, n))()
     st = (ctypes.c_int32 * max(1, n))()
-    _check(_lib.tdct_server_replay(server, ra, at, n, int(keep_outputs), tk, lat, st),
+    bs = (ctypes.c_int32 * max(1, n))()
+    _check(_lib.tdct_server_replay(server, ra, at, n, int(keep_outputs), tk, lat, st, bs),
            "tdct_server_replay")
-    return list(tk)[:n], list(lat)[:n], list(st)[:n]
+    out = (list(tk)[:n], list(lat)[:n], list(st)[:n])
+    return out + (list(bs)[:n],) if with_batch else out

@@ -42,9 +42,15 @@ __global__ __launch_bounds__(256) void probe_kernel(const v4u* __restrict__ a, v
         const v4u v = ld_nt4(a + i);
         st_nt4(b + i, v);
         st_nt4(b + units + i, v);
-    } else {
+    } else if constexpr (KIND == TDCT_PROBE_R2W1) {
         const v4u v = ld_nt4(a + i), w = ld_nt4(a + units + i);
         st_nt4(b + i, v ^ w);
+    } else {
+        // three output streams: a round trip writing coefficients and pixels
+        const v4u v = ld_nt4(a + i);
+        st_nt4(b + i, v);
+        st_nt4(b + units + i, v);
+        st_nt4(b + 2 * units + i, v);
     }
 }
 
@@ -75,6 +81,7 @@ int tdct_stream_probe(int32_t kind, const void* src, void* dst, int64_t units, v
         case TDCT_PROBE_WRITE: return launch_probe<TDCT_PROBE_WRITE>(a, b, (uint64_t)units, s);
         case TDCT_PROBE_R1W2: return launch_probe<TDCT_PROBE_R1W2>(a, b, (uint64_t)units, s);
         case TDCT_PROBE_R2W1: return launch_probe<TDCT_PROBE_R2W1>(a, b, (uint64_t)units, s);
+        case TDCT_PROBE_R1W3: return launch_probe<TDCT_PROBE_R1W3>(a, b, (uint64_t)units, s);
         default: return TDCT_EINVAL;
     }
 }

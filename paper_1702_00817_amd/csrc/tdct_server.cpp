@@ -468,12 +468,21 @@ double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
     double next_deadline = -1;
     for (Slot& sl : s->slots) {
         if (sl.busy || s->admitted.empty()) continue;
-        const int maxb = s->cfg.batching ? std::max(1, s->cfg.max_batch) : 1;
+        int maxb = s->cfg.batching ? std::max(1, s->cfg.max_batch) : 1;
         const double oldest = s->reqs[s->admitted.front()].submit_us;
         if (s->cfg.batching && s->cfg.max_wait_us > 0 && (int)s->admitted.size() < maxb &&
             now - oldest < s->cfg.max_wait_us && !s->stop) {
             next_deadline = oldest + s->cfg.max_wait_us;
             break;
+        }
+        // Without a batching window, a free slot takes its share of the
+        // admitted requests over all slots: requests the slots can take one
+        // by one launch alone (the plain kernel, no table upload), and
+        // batches form only under a backlog.
+        if (s->cfg.batching && s->cfg.max_wait_us == 0) {
+            const int64_t share = ((int64_t)s->admitted.size() + (int64_t)s->slots.size() - 1) /
+                                  (int64_t)s->slots.size();
+            maxb = (int)std::min<int64_t>(maxb, std::max<int64_t>(1, share));
         }
         items.clear();
         int64_t batch_px = 0;
@@ -1206,7 +1215,7 @@ void tdct_server_destroy(tdct_server* s) {
 
 static int server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us,
                          int32_t n, int32_t keep_outputs, uint64_t* tickets_out,
-                         double* latency_us, int32_t* status) {
+                         double* latency_us, int32_t* status, int32_t* batch_out) {
     if (!s || n < 0 || (n > 0 && (!reqs || !arrival_us))) return TDCT_EINVAL;
     int64_t kept = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -1240,6 +1249,7 @@ static int server_replay(tdct_server* s, const tdct_request* reqs, const double*
         const bool ok = sub[k] == TDCT_OK && it != s->reqs.end();
         if (latency_us) latency_us[k] = ok ? it->second.done_us - it->second.submit_us : -1.0;
         if (status) status[k] = ok ? it->second.status : sub[k];
+        if (batch_out) batch_out[k] = ok ? it->second.batch_size : 0;
         if (ok && !keep_outputs) s->reqs.erase(it);
     }
     return TDCT_OK;
@@ -1247,9 +1257,10 @@ static int server_replay(tdct_server* s, const tdct_request* reqs, const double*
 
 int tdct_server_replay(tdct_server* s, const tdct_request* reqs, const double* arrival_us, int32_t n,
                        int32_t keep_outputs, uint64_t* tickets_out, double* latency_us,
-                       int32_t* status) {
+                       int32_t* status, int32_t* batch_size) {
     return abi_call([&]() -> int {
-        return server_replay(s, reqs, arrival_us, n, keep_outputs, tickets_out, latency_us, status);
+        return server_replay(s, reqs, arrival_us, n, keep_outputs, tickets_out, latency_us, status,
+                             batch_size);
     });
 }
 

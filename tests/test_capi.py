@@ -250,6 +250,24 @@ def test_fake_server_launch_failure_waits_for_queued_work(tdct):
         tdct.tdct_server_destroy(s)
 
 
+def test_fake_server_spreads_requests_over_free_slots(tdct):
+    """Without a batching window a free slot takes ceil(admitted / slots)
+    requests: requests that free slots can take one by one launch alone, and
+    a backlog is shared out in batches of about equal size."""
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 24, streams=4, max_batch=16, fake_device_us=30000))
+    try:
+        first = [tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 32, 32)) for _ in range(4)]
+        time.sleep(0.005)  # all four slots busy for 30 ms
+        backlog = [tdct.tdct_server_submit(s, _req(tdct, tdct.OP_ENCODE, 32, 32)) for _ in range(16)]
+        tdct.tdct_server_drain(s)
+        assert [tdct.tdct_server_poll(s, t).batch_size for t in first] == [1, 1, 1, 1]
+        sizes = [tdct.tdct_server_poll(s, t).batch_size for t in backlog]
+        assert max(sizes) == 4 and min(sizes) >= 1
+        assert tdct.tdct_server_stats(s)["completed"] == 20
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
 def test_fake_server_batches_requests_that_arrive_together(tdct):
     s = tdct.tdct_server_create(tdct.server_cfg(1 << 26, streams=1, max_batch=16, max_wait_us=20000,
                                                 fake_device_us=100))
