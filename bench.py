@@ -20,16 +20,23 @@ and, unless --no-extras:
   fused_roundtrip  encode + decode fused with no coefficients in HBM;
   per_image     the same 64-image batch with one plain launch per image;
   forward       the int32 forward transform alone over the same batch (5 B/px);
+  plain         the plain encode and decode calls on one image of 4096^2,
+                8192^2 and 16384^2;
   latency_512   one 512 x 512 image: per-call latency of each plain entry
                 point, and the PSNR of a zonal keep-10 reconstruction;
-  ceiling       stream probes: the part's practical copy/read/write rates;
+  ceiling       stream probes: the part's practical copy/read/write rates for
+                the codec's access mixes (1:1, 1:2, 2:1, 1:3);
   video         256 4:2:0 frames to int8 zigzag, one graph vs one launch per plane;
   batched       10,000 ragged images as one persistent launch replayed from a
                 hipGraph vs one plain launch per image;
-  serving       Poisson request streams served with continuous batching, with a
-                plain launch per request, by the resident kernel, and with host
-                payloads over PCIe: p50/p99 latency and Gpixel/s;
+  serving       Poisson request streams (60 s per rate) served with continuous
+                batching and with a plain launch per request, and (shorter) by
+                the resident kernel and with host payloads over PCIe:
+                p50/p99/p99.9 latency, the tail's make-up, Gpixel/s;
   quality       (--quality) the zonal-coding sweep against the exact DCT.
+cpu_baseline also holds the oracle beside the 512 x 512 latency leg, the
+ragged batch and the video frames, and its check of the served outputs (a
+seeded 1 % of each trace plus every request of 32 Mpx or more).
 """
 from __future__ import annotations
 
@@ -335,7 +342,7 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
         tdct.tdct_plan_free(plan)
     del src, coef, dst
     gbs = 4 * px / graph_s / 1e9
-    return {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
+    return (buf, off, strides, sizes, qs), {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
                          "frac": round(gbs / 8000.0, 4)},
             "graph_gpx_s": round(px / graph_s / 1e9, 2), "graph_ms": round(graph_s * 1e3, 3),
@@ -345,17 +352,19 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
             "speedup": round(per_s / graph_s, 2), "bytes_per_px": 4}
 
 
-PROBES = (("copy", 32), ("read", 16), ("write", 16), ("read1_write2", 48), ("read2_write1", 48))
+PROBES = (("copy", 32), ("read", 16), ("write", 16), ("read1_write2", 48), ("read2_write1", 48),
+          ("read1_write3", 64))
 
 
 def ceiling_leg(tdct, torch, stream, mib=1024, reps=5, names=None):
     """HBM ceilings on this part: the codec's access mixes without arithmetic."""
     units = (mib << 20) // 16
     a = torch.ones(2 * units * 16, dtype=torch.uint8, device="cuda")
-    b = torch.empty_like(a)
+    b = torch.empty(3 * units * 16, dtype=torch.uint8, device="cuda")
     out = {}
     kinds = {"copy": tdct.PROBE_COPY, "read": tdct.PROBE_READ, "write": tdct.PROBE_WRITE,
-             "read1_write2": tdct.PROBE_R1W2, "read2_write1": tdct.PROBE_R2W1}
+             "read1_write2": tdct.PROBE_R1W2, "read2_write1": tdct.PROBE_R2W1,
+             "read1_write3": tdct.PROBE_R1W3}
     for name, per_unit in PROBES:
         if names and name not in names:
             continue
@@ -377,6 +386,14 @@ def ceiling_leg(tdct, torch, stream, mib=1024, reps=5, names=None):
 # 2.4 GHz = 39.3 T lane-operations/s (non-packed 32-bit; a wave64 VALU
 # instruction occupies one SIMD for 4 clocks).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# The method's own integer operations per 8x8 block of a round trip without
+# stored coefficients: level shift 1 (on the DC term), forward 16 x 14 = 224
+# add/sub (Table 1's 14 per 8-point pass), quantiser 64 shifts (D^2 fold) +
+# 64 rounding divisions, dequantiser 64 multiplies, inverse 224 add/sub,
+# rounding offset 1 (on the DC term), 64 shifts by 6 and 128 clamp
+# comparisons: 834 per 64 pixels.
+ROUNDTRIP_ALG_OPS_PER_BLOCK = 1 + 224 + 64 + 64 + 64 + 224 + 1 + 64 + 128
 
 
 def load_valu(name: str):
@@ -428,9 +445,16 @@ def fused_leg(tdct, torch, W, stream, reps=10, tune=None):
     if valu:
         lane_ops = valu["valu_insts_per_launch"] * 64
         achieved = lane_ops / (ms / 1e3) / 1e12
+        alg = ROUNDTRIP_ALG_OPS_PER_BLOCK / 64
         alu = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
                "unit": "T VALU lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-               "valu_lane_ops_per_px": round(lane_ops / px, 3)}
+               "valu_lane_ops_per_px": round(lane_ops / px, 3),
+               # the method's own operation count at the same rate; above the
+               # issued count because packed int16 codes two blocks per
+               # instruction and the fp32 decoder half fuses multiply-adds and
+               # round/clamp/pack
+               "algorithmic_ops_per_px": round(alg, 3),
+               "algorithmic_tops": round(alg * px / (ms / 1e3) / 1e12, 2)}
         roof = dict(alu, hbm=hbm) if alu["frac"] > hbm["frac"] else dict(hbm, valu=alu)
     return {"kernel": "batch_kernel<32, %s> (round trip, coefficients kept in registers)"
             % ("true" if tune.get("pixel_cache") else "false"), "tune": tune,
@@ -518,6 +542,7 @@ def video_leg(tdct, torch, stream, frames=256, reps=5):
         tdct.tdct_plan_free(plan)
     n = host.size
     del src, out
+    ctx = (host, v, frames)
     gbs = 2 * n / graph_s / 1e9
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
             "frac": round(gbs / 8000.0, 4)}
@@ -528,7 +553,7 @@ def video_leg(tdct, torch, stream, frames=256, reps=5):
         roof["valu"] = {"achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
                         "unit": "T VALU lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                         "valu_lane_ops_per_sample": round(lane_ops / n, 3)}
-    return {"frames": frames, "samples": n, "tune": tune,
+    return ctx, {"frames": frames, "samples": n, "tune": tune,
             "graph_gsamples_s": round(n / graph_s / 1e9, 1), "graph_ms": round(graph_s * 1e3, 3),
             "graph_gbs": round(gbs, 1),
             "per_plane_gsamples_s": round(n / per_s / 1e9, 1), "per_plane_ms": round(per_s * 1e3, 3),
@@ -603,107 +628,445 @@ def quality_leg(tdct, torch, stream, n_images=45, side=512, rs=range(2, 46)):
             "gpu_launches": 2 * n_images * len(rs), "table": rows}
 
 
-def serving_leg(tdct, torch, seconds, rates=(200, 1000, 5000), streams=4, resident_workers=0,
-                modes=("batched", "per_request", "resident", "host_io_batched")):
-    """Poisson encode/decode requests served by continuous batching, by one
-    plain launch per request and by the resident polling kernel, with
-    device-resident payloads; and the same stream with host-resident payloads
-    copied in and out over PCIe (host_io_batched, the PCIe-inclusive rate)."""
-    import numpy as np
+SERVING_POOL = 4          # payload planes of the serving leg
+SERVING_SIDE = 8192       # their side (the largest request side)
 
-    def cfg(mode):
-        if mode == "resident":
-            return tdct.server_cfg(64 << 30, resident=1, resident_workers=resident_workers,
-                                   resident_idle_us=100000)
-        # requests have ragged widths: batch launches take cached pixel
-        # accesses (burst capacity +5-8 % measured; lone requests use the
-        # plain kernel either way)
-        return tdct.server_cfg(64 << 30, streams=streams, max_batch=64, max_wait_us=0,
-                               batching=0 if mode == "per_request" else 1, max_batch_px=MAX_BATCH_PX,
-                               tune=dict(pixel_cache=1))
 
+def serving_pool(tdct, torch):
+    """Device-resident payloads of the serving leg: SERVING_POOL blob planes
+    of 8192^2 (encode inputs; a request is the top-left w x h window) and the
+    encoder's output of each under Q = 1 + (1 + k)(i + j) (decode inputs; a
+    request decodes the first (w/8)(h/8) blocks as a w x h image)."""
     import synth
-    max_side = 8192
-    pool_n = 4
-    log("serving: building a payload pool of %d planes of %d^2" % (pool_n, max_side))
-    pool = [torch.from_numpy(synth.plane(max_side, max_side, 5000 + k)).cuda() for k in range(pool_n)]
-    # decode inputs: encoder output of the pool planes (any int16 is a valid input)
-    nblk = (max_side // 8) ** 2
+    log("serving: building a payload pool of %d planes of %d^2" % (SERVING_POOL, SERVING_SIDE))
+    host = [synth.plane(SERVING_SIDE, SERVING_SIDE, 5000 + k) for k in range(SERVING_POOL)]
+    pool = [torch.from_numpy(p).cuda() for p in host]
+    nblk = (SERVING_SIDE // 8) ** 2
     coefs = []
-    for k in range(pool_n):
+    for k in range(SERVING_POOL):
         c = torch.empty((nblk, 64), dtype=torch.int16, device="cuda")
-        tdct.tdct_quantise(pool[k], max_side, max_side, max_side, synth.qtable(1, 1 + k), 64, c)
+        tdct.tdct_quantise(pool[k], SERVING_SIDE, SERVING_SIDE, SERVING_SIDE, synth.qtable(1, 1 + k), 64, c)
         coefs.append(c)
     torch.cuda.synchronize()
-    # host-resident payloads for the PCIe-inclusive mode: pinned copies of the
-    # pool, and a few pinned output buffers of the largest size reused in turn
-    # (requests in flight may overwrite each other's host copies: timing only)
-    hpool = [p.cpu().pin_memory() for p in pool]
-    hcoefs = [c.cpu().pin_memory() for c in coefs]
-    houts = [torch.empty(2 * max_side * max_side, dtype=torch.uint8).pin_memory() for _ in range(4)]
-    out = {}
+    return {"host": host, "pool": pool, "coefs": coefs}
+
+
+def serving_requests(tdct, tr, P, idx=None, host_io=None):
+    """The trace's requests (or those at `idx`) as one ctypes array: request k
+    encodes or decodes a window of payload k mod SERVING_POOL with
+    Q = 1 + s(i + j), keep 64. host_io: (pinned pool copies, pinned coefficient
+    copies, pinned output buffers reused in turn)."""
+    import synth
+    qt = {s: tdct.qtable(synth.qtable(1, s)) for s in range(1, 9)}
+    idx = range(len(tr["t"])) if idx is None else idx
+    idx = list(idx)
+    ra = tdct.request_array(len(idx))
+    pin = [p.data_ptr() for p in P["pool"]]
+    cin = [c.data_ptr() for c in P["coefs"]]
+    if host_io:
+        hp, hc, ho = host_io
+        pin = [p.data_ptr() for p in hp]
+        cin = [c.data_ptr() for c in hc]
+        outs = [o.data_ptr() for o in ho]
+    ops, ws, hs, ss = tr["op"], tr["w"], tr["h"], tr["s"]
+    for j, k in enumerate(idx):
+        r = ra[j]
+        w, h, p = int(ws[k]), int(hs[k]), k % SERVING_POOL
+        r.w, r.h, r.keep, r.Q = w, h, 64, qt[int(ss[k])]
+        if ops[k] == 0:
+            r.op, r.input, r.in_stride = tdct.OP_ENCODE, pin[p], SERVING_SIDE
+        else:
+            r.op, r.input, r.in_stride = tdct.OP_DECODE, cin[p], w
+        if host_io:
+            r.host_io, r.host_output = 1, outs[k % len(outs)]
+    return ra
+
+
+def _pct(v, q):
+    import numpy as np
+    return round(float(np.percentile(v, q)), 1) if len(v) else None
+
+
+def serving_cfg(tdct, mode, streams=4, resident_workers=0):
+    if mode == "resident":
+        return tdct.server_cfg(64 << 30, resident=1, resident_workers=resident_workers,
+                               resident_idle_us=100000)
+    # requests have ragged widths: batch launches take cached pixel accesses
+    # (burst capacity +5-8 % measured; lone requests use the plain kernel
+    # either way)
+    return tdct.server_cfg(64 << 30, streams=streams, max_batch=64, max_wait_us=0,
+                           batching=0 if mode == "per_request" else 1, max_batch_px=MAX_BATCH_PX,
+                           tune=dict(pixel_cache=1))
+
+
+def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), streams=4,
+                resident_workers=0, modes=("batched", "per_request", "resident", "host_io_batched")):
+    """Poisson encode/decode requests (the serving workload: sides log-uniform
+    multiples of 8 in [32, 8192], aspect <= 4, s in {1..8}) served by
+    continuous batching and by one plain launch per request for `seconds`
+    per rate, with device-resident payloads; by the resident polling kernel
+    and with host payloads copied over PCIe (host_io_batched, the
+    PCIe-inclusive rate) for `aux_seconds` per rate. Per mode: latency
+    percentiles, the tail's make-up (share of p99-and-above requests served in
+    a batch of more than one, their mean size) and small-request percentiles.
+    Returns (result, context for the oracle check)."""
+    import numpy as np
+
+    import synth
+    P = serving_pool(tdct, torch)
+    hp = hc = ho = None
+    if "host_io_batched" in modes:
+        # pinned copies of the payloads and a few pinned output buffers of the
+        # largest size reused in turn (requests in flight may overwrite each
+        # other's host copies: timing only)
+        hp = [p.cpu().pin_memory() for p in P["pool"]]
+        hc = [c.cpu().pin_memory() for c in P["coefs"]]
+        ho = [torch.empty(2 * SERVING_SIDE ** 2, dtype=torch.uint8).pin_memory() for _ in range(4)]
+    out, traces = {}, {}
     for rate in rates:
-        tr = synth.serving_trace(rate, seconds, seed=5)
-        reqs = []
-        for k in range(len(tr["t"])):
-            w, h, s = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k])
-            p = k % pool_n
-            if tr["op"][k] == 0:
-                reqs.append(tdct.request(tdct.OP_ENCODE, w, h, pool[p], synth.qtable(1, s), keep=64,
-                                         in_stride=max_side))
-            else:
-                reqs.append(tdct.request(tdct.OP_DECODE, w, h, coefs[p], synth.qtable(1, s)))
-        arrival = (tr["t"] * 1e6).tolist()
-        px = int((tr["w"] * tr["h"]).sum())
-        res = {"requests": len(reqs), "mpx_mean": round(px / max(1, len(reqs)) / 1e6, 3)}
-        hreqs = []
-        for k in range(len(tr["t"])):
-            w, h, s = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k])
-            p, o = k % pool_n, houts[k % len(houts)].data_ptr()
-            if tr["op"][k] == 0:
-                hreqs.append(tdct.request(tdct.OP_ENCODE, w, h, hpool[p].data_ptr(), synth.qtable(1, s),
-                                          keep=64, in_stride=max_side, host_output=o))
-            else:
-                hreqs.append(tdct.request(tdct.OP_DECODE, w, h, hcoefs[p].data_ptr(), synth.qtable(1, s),
-                                          host_output=o))
+        res = {}
         for mode in modes:
-            rq = hreqs if mode == "host_io_batched" else reqs
-            srv = tdct.tdct_server_create(cfg(mode))
+            secs = seconds if mode in ("batched", "per_request") else aux_seconds
+            tr = synth.serving_trace(rate, secs, seed=5)
+            traces[(rate, secs)] = tr
+            px = (tr["w"] * tr["h"]).astype(np.int64)
+            ra = serving_requests(tdct, tr, P, host_io=(hp, hc, ho) if mode == "host_io_batched" else None)
+            arrival = (tr["t"] * 1e6).tolist()
+            srv = tdct.tdct_server_create(serving_cfg(tdct, mode, streams, resident_workers))
             try:
                 t0 = time.perf_counter()
-                _, lat, st = tdct.tdct_server_replay(srv, rq, arrival)
+                _, lat, st, bs = tdct.tdct_server_replay(srv, ra, arrival, with_batch=True)
                 wall = time.perf_counter() - t0
                 stats = tdct.tdct_server_stats(srv)
             finally:
                 tdct.tdct_server_destroy(srv)
-            lat = np.array([x for x, s_ in zip(lat, st) if s_ == 0])
-            res[mode] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
-                         "p99_us": round(float(np.percentile(lat, 99)), 1),
-                         "p999_us": round(float(np.percentile(lat, 99.9)), 1),
-                         "failed": int(sum(1 for s_ in st if s_ != 0)),
-                         "delivered_gpx_s": round(px / wall / 1e9, 3),
-                         "batches": stats["batches"], "mean_batch": round(stats["mean_batch"], 2),
-                         "arena_high_water_gb": round(stats["arena_high_water"] / 1e9, 3)}
+            ok = np.array(st) == 0
+            lat, bs, pxo = np.array(lat)[ok], np.array(bs)[ok], px[ok]
+            p99 = np.percentile(lat, 99) if len(lat) else 0
+            tail = lat >= p99
+            small = pxo < (1 << 20)
+            res[mode] = {"seconds": secs, "requests": int(len(px)), "mpx_mean": round(float(px.mean()) / 1e6, 3),
+                         "p50_us": _pct(lat, 50), "p99_us": _pct(lat, 99), "p999_us": _pct(lat, 99.9),
+                         "failed": int((~ok).sum()),
+                         "delivered_gpx_s": round(float(px.sum()) / wall / 1e9, 3),
+                         "batches": stats["batches"], "mean_batch": round(stats["mean_batch"], 3),
+                         "arena_high_water_gb": round(stats["arena_high_water"] / 1e9, 3),
+                         "tail": {"requests": int(tail.sum()),
+                                  "in_batches_share": round(float((bs[tail] > 1).mean()), 3) if tail.any() else None,
+                                  "mpx_mean": round(float(pxo[tail].mean()) / 1e6, 2) if tail.any() else None},
+                         "under_1mpx": {"requests": int(small.sum()), "p50_us": _pct(lat[small], 50),
+                                        "p99_us": _pct(lat[small], 99)}}
+            log("serving %d req/s %s: %s" % (rate, mode, json.dumps(res[mode])))
         if rate == max(rates):
-            # capacity: the same requests all arriving at once (closed burst)
+            # capacity: the same requests all arriving at once (closed burst),
+            # the aux-length trace
+            tr = synth.serving_trace(rate, aux_seconds, seed=5)
+            ra = serving_requests(tdct, tr, P)
+            px = float((tr["w"] * tr["h"]).sum())
             for mode in modes:
                 if mode == "host_io_batched":
                     continue
-                srv = tdct.tdct_server_create(cfg(mode))
+                srv = tdct.tdct_server_create(serving_cfg(tdct, mode, streams, resident_workers))
                 try:
                     t0 = time.perf_counter()
-                    _, lat, st = tdct.tdct_server_replay(srv, reqs, [0.0] * len(reqs))
+                    _, lat, st = tdct.tdct_server_replay(srv, ra, [0.0] * len(ra))
                     wall = time.perf_counter() - t0
                     stats = tdct.tdct_server_stats(srv)
                 finally:
                     tdct.tdct_server_destroy(srv)
-                res["burst_" + mode] = {"gpx_s": round(px / wall / 1e9, 1), "wall_ms": round(wall * 1e3, 1),
+                res["burst_" + mode] = {"requests": len(ra), "gpx_s": round(px / wall / 1e9, 1),
+                                        "wall_ms": round(wall * 1e3, 1),
                                         "mean_batch": round(stats["mean_batch"], 2),
                                         "failed": int(sum(1 for s_ in st if s_ != 0))}
         out[str(rate)] = res
-        log("serving %d req/s: %s" % (rate, json.dumps(res)))
-    return {"seconds_per_rate": seconds, "streams": streams, "budget_gb": 64,
-            "resident_workers": resident_workers or "one per CU", "rates": out}
+    result = {"seconds_per_rate": {"batched": seconds, "per_request": seconds, "resident": aux_seconds,
+                                   "host_io_batched": aux_seconds},
+              "streams": streams, "budget_gb": 64,
+              "resident_workers": resident_workers or "one per CU", "rates": out}
+    return result, {"P": P, "traces": traces, "seconds": seconds, "streams": streams}
+
+
+def _hip_memcpy():
+    """hipMemcpy of the HIP runtime torch loaded (device-to-device copies of
+    arena outputs into torch buffers for the checks)."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+    lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    lib.hipMemcpy.restype = ctypes.c_int
+    return lib.hipMemcpy
+
+
+def _oracle_threads():
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def cpu_baseline_serving(tdct, torch, ctx, rates, frac=0.01, big_px=32 << 20, direct_n=64):
+    """The served outputs against the oracle, outside the timed replays: for
+    every rate, a seeded `frac` of the trace plus every request of at least
+    32 Mpx is served again (same configuration, all at once, outputs kept),
+    in the batched and in the per-request mode, and each output is compared
+    in full with the oracle's.
+
+    The oracle encodes every payload plane under every table the trace uses
+    and decodes, block by block, its own encoding of each plane (what the
+    decode requests of that payload carry) under every table; a request's
+    expected output is then its window (blocks depend only on their own 64
+    pixels). The GPU's decode inputs are checked against the oracle's
+    encoding too. The oracle is also timed directly on `direct_n` sampled
+    requests (its px/s on the request mix)."""
+    import numpy as np
+
+    import oracle as O
+    import synth
+    P = ctx["P"]
+    threads = _oracle_threads()
+    side = SERVING_SIDE
+    nb = side // 8
+    nblk = nb * nb
+    t0 = time.perf_counter()
+    E, D = {}, {}
+    for p in range(SERVING_POOL):
+        for s_ in range(1, 9):
+            E[(p, s_)] = O.quantise(P["host"][p], synth.qtable(1, s_), 64, threads=threads)
+    for p in range(SERVING_POOL):
+        qin = E[(p, 1 + p)]
+        for s_ in range(1, 9):
+            plane = O.inverse(qin, synth.qtable(1, s_), side, side, threads=threads)
+            D[(p, s_)] = np.ascontiguousarray(plane.reshape(nb, 8, nb, 8).transpose(0, 2, 1, 3))
+    t_planes = time.perf_counter() - t0
+    planes_px = 2 * len(E) * side * side
+    Ed = {k: torch.from_numpy(v).cuda().view(nb, nb, 64) for k, v in E.items()}
+    Dd = {k: torch.from_numpy(v).cuda().view(nblk, 8, 8) for k, v in D.items()}
+    inputs_ok = all(torch.equal(P["coefs"][p], Ed[(p, 1 + p)].view(nblk, 64)) for p in range(SERVING_POOL))
+    memcpy = _hip_memcpy()
+    buf = torch.empty(2 * side * side, dtype=torch.uint8, device="cuda")
+
+    def matches(tr, k, ptr, nbytes):
+        w, h, s_, p = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k]), k % SERVING_POOL
+        torch.cuda.synchronize()
+        assert memcpy(buf.data_ptr(), ptr, nbytes, 3) == 0  # device to device
+        if tr["op"][k] == 0:
+            got = buf[:nbytes].view(torch.int16).view(h // 8, w // 8, 64)
+            return nbytes == 2 * w * h and torch.equal(got, Ed[(p, s_)][:h // 8, :w // 8])
+        got = buf[:nbytes].view(h // 8, 8, w // 8, 8)
+        want = Dd[(p, s_)][:(w // 8) * (h // 8)].view(h // 8, w // 8, 8, 8).permute(0, 2, 1, 3)
+        return nbytes == w * h and torch.equal(got, want)
+
+    out = {}
+    direct_pool = []
+    for rate in rates:
+        tr = ctx["traces"][(rate, ctx["seconds"])]
+        n = len(tr["t"])
+        px = (tr["w"] * tr["h"]).astype(np.int64)
+        rng = np.random.default_rng([5, rate, 1])
+        rand = rng.choice(n, int(np.ceil(frac * n)), replace=False)
+        big = np.nonzero(px >= big_px)[0]
+        sample = np.union1d(rand, big)
+        direct_pool += [(rate, int(k)) for k in rand[:direct_n]]
+        outb = np.where(tr["op"] == 0, 2 * px, px)
+        res = {"requests": int(len(sample)), "random": int(len(rand)), "at_least_32mpx": int(len(big)),
+               "gpx": round(float(px[sample].sum()) / 1e9, 2)}
+        for mode in ("batched", "per_request"):
+            bad = 0
+            srv = tdct.tdct_server_create(serving_cfg(tdct, mode, ctx["streams"]))
+            try:
+                start = 0
+                while start < len(sample):
+                    # outputs of one chunk stay in the 64 GB arena until compared
+                    stop, acc = start, 0
+                    while stop < len(sample) and (stop == start or acc + outb[sample[stop]] <= 48 << 30):
+                        acc += (int(outb[sample[stop]]) + 255) // 256 * 256
+                        stop += 1
+                    chunk = [int(k) for k in sample[start:stop]]
+                    ra = serving_requests(tdct, tr, P, idx=chunk)
+                    tickets, _, st = tdct.tdct_server_replay(srv, ra, [0.0] * len(chunk), keep_outputs=True)
+                    for k, t, st_ in zip(chunk, tickets, st):
+                        r = tdct.tdct_server_poll(srv, t)
+                        if st_ != 0 or not matches(tr, k, r.output, r.output_bytes):
+                            bad += 1
+                        tdct.tdct_server_release(srv, t)
+                    start = stop
+            finally:
+                tdct.tdct_server_destroy(srv)
+            res["mismatches_" + mode] = bad
+        out[str(rate)] = res
+        log("serving check %d req/s: %s" % (rate, json.dumps(res)))
+    # the oracle directly on sampled requests: its px/s on the request mix
+    dpx, t0 = 0, time.perf_counter()
+    direct_bad = 0
+    for rate, k in direct_pool:
+        tr = ctx["traces"][(rate, ctx["seconds"])]
+        w, h, s_, p = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k]), k % SERVING_POOL
+        Q = synth.qtable(1, s_)
+        if tr["op"][k] == 0:
+            q = O.quantise(P["host"][p][:h], Q, 64, w=w, threads=threads)
+            direct_bad += not np.array_equal(q.reshape(h // 8, w // 8, 64), E[(p, s_)].reshape(nb, nb, 64)[:h // 8, :w // 8])
+        else:
+            nbk = (w // 8) * (h // 8)
+            x = O.inverse(E[(p, 1 + p)][:nbk], Q, w, h, threads=threads)
+            want = D[(p, s_)].reshape(nblk, 8, 8)[:nbk].reshape(h // 8, w // 8, 8, 8).transpose(0, 2, 1, 3)
+            direct_bad += not np.array_equal(x.reshape(h // 8, 8, w // 8, 8), want)
+        dpx += w * h
+    t_direct = time.perf_counter() - t0
+    del Ed, Dd, buf
+    torch.cuda.empty_cache()
+    return {"kind": "oracle", "cores": threads,
+            "decode_inputs_equal_oracle": bool(inputs_ok), "rates": out,
+            "oracle_direct": {"requests": len(direct_pool), "gpx_s": round(dpx / t_direct / 1e9, 4),
+                              "mismatches_vs_planes": int(direct_bad)},
+            "oracle_planes": {"gpx_s": round(planes_px / t_planes / 1e9, 4), "seconds": round(t_planes, 2)},
+            "sample": "seeded %.0f %% of each %g-s trace plus every request of >= 32 Mpx, served again "
+                      "(batched and per-request modes) and compared in full with windows of the oracle's "
+                      "whole-plane encodings and block-wise decodings (%d threads)"
+                      % (100 * frac, ctx["seconds"], threads)}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def cpu_baseline_512(reps=20):
+    """The oracle on the 512 x 512 image (seed 1) with the latency leg's
+    calls: median time per call on all cores and on one core."""
+    import numpy as np
+
+    import oracle as O
+    import synth
+    img = synth.plane(512, 512, 1)
+    one = np.ones(64, np.uint16)
+    q10 = O.quantise(img, one, 10)
+    out = {"side": 512, "reps": reps}
+    for label, th in (("all_cores", _oracle_threads()), ("single_core", 1)):
+        calls = {"forward_int32": lambda: O.forward(img, threads=th),
+                 "quantise_keep10": lambda: O.quantise(img, one, 10, threads=th),
+                 "inverse": lambda: O.inverse(q10, one, 512, 512, threads=th),
+                 "roundtrip_keep10": lambda: O.roundtrip(img, one, 10, threads=th)}
+        r = {}
+        for name, f in calls.items():
+            f()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                f()
+                ts.append(time.perf_counter() - t0)
+            r[name + "_us"] = round(1e6 * sorted(ts)[reps // 2], 1)
+        out[label] = dict(r, cores=th)
+    return out
+
+
+def _pool_rate(fn, items, threads, min_s):
+    """Runs fn(item) over items on `threads` host threads (one oracle call
+    each, single-threaded) until min_s seconds have passed; returns
+    (units done, seconds, items done)."""
+    from concurrent.futures import ThreadPoolExecutor
+    done, units = 0, 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        while done < len(items) and time.perf_counter() - t0 < min_s:
+            chunk = items[done:done + 4 * threads]
+            units += sum(ex.map(fn, chunk))
+            done += len(chunk)
+    return units, time.perf_counter() - t0, done
+
+
+def cpu_baseline_ragged(ctx, min_s=3.0):
+    """The oracle on the ragged images (encode + decode with coefficients,
+    as the batched leg), images spread over the host threads, and on one
+    core."""
+    import oracle as O
+    import synth
+    buf, off, strides, sizes, qs = ctx
+
+    def one(i):
+        img = synth.batch_view(buf, off, strides, sizes, i)
+        O.roundtrip(img, qs[i], 64)
+        return int(sizes[i][0]) * int(sizes[i][1])
+
+    items = list(range(len(sizes)))
+    th = _oracle_threads()
+    px, dt, done = _pool_rate(one, items, th, min_s)
+    px1, dt1, done1 = _pool_rate(one, items, 1, min_s / 3)
+    return {"value": round(px / dt / 1e9, 4), "unit": "Gpixel/s", "cores": th, "kind": "oracle",
+            "sample": "encode+decode of the first %d of the 10,000 ragged images (%.2f Gpx, %.1f s), "
+                      "one image per thread" % (done, px / 1e9, dt),
+            "single_core": {"value": round(px1 / dt1 / 1e9, 4), "unit": "Gpixel/s",
+                            "sample": "first %d images in %.1f s" % (done1, dt1)}}
+
+
+def cpu_baseline_video(ctx, min_s=3.0):
+    """The oracle's int8 zigzag encoder on the 4:2:0 frames (luma and chroma
+    tables as the video leg), planes spread over the host threads, and on
+    one core."""
+    import oracle as O
+    host, v, frames = ctx
+    w, h = v.w, v.h
+    fbytes = w * h + 2 * (w // 2) * (h // 2)
+    planes = []
+    for f in range(frames):
+        qy, qc = v.qtables(f)
+        o = f * fbytes
+        planes += [(o, w, h, qy), (o + w * h, w // 2, h // 2, qc),
+                   (o + w * h + (w // 2) * (h // 2), w // 2, h // 2, qc)]
+
+    def one(pl):
+        o, pw, ph, Q = pl
+        O.quantise_i8_zigzag(host[o:o + pw * ph].reshape(ph, pw), Q)
+        return pw * ph
+
+    th = _oracle_threads()
+    n, dt, done = _pool_rate(one, planes, th, min_s)
+    n1, dt1, done1 = _pool_rate(one, planes, 1, min_s / 3)
+    return {"value": round(n / dt / 1e9, 4), "unit": "Gsample/s", "cores": th, "kind": "oracle",
+            "sample": "int8 zigzag encode of the first %d of the 768 planes (%.2f G samples, %.1f s), "
+                      "one plane per thread" % (done, n / 1e9, dt),
+            "single_core": {"value": round(n1 / dt1 / 1e9, 4), "unit": "Gsample/s",
+                            "sample": "first %d planes in %.1f s" % (done1, dt1)}}
+
+
+def plain_leg(tdct, torch, stream, sides=(4096, 8192, 16384), reps=10):
+    """One image per call through the plain C-ABI calls: tdct_quantise
+    (encode, keep 64) and tdct_inverse (decode) on one blob-field image of
+    4096^2, 8192^2 and 16384^2, Q = 1 + 3(i + j). Each is the median of `reps`
+    event-timed calls queued back to back behind a spin kernel (so the events
+    see device time only); 3 B/px algorithmic against 8 TB/s."""
+    import synth
+    Q = tdct.qtable(synth.qtable(1, 3))
+    out = {}
+    for side in sides:
+        src = torch.from_numpy(synth.plane(side, side, 4242)).cuda()
+        q = torch.empty(((side // 8) ** 2, 64), dtype=torch.int16, device="cuda")
+        dst = torch.empty_like(src)
+        px = side * side
+        calls = {"encode": lambda: tdct.tdct_quantise(src, side, side, side, Q, 64, q, stream),
+                 "decode": lambda: tdct.tdct_inverse(q, Q, side, side, dst, side, stream)}
+        r = {}
+        for name, f in calls.items():
+            f()
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            with torch.cuda.stream(stream):
+                torch.cuda._sleep(1 << 21)
+            ev[0].record(stream)
+            for k in range(reps):
+                f()
+                ev[k + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))[reps // 2]
+            gbs = 3 * px / (ms / 1e3) / 1e9
+            r[name] = {"ms": round(ms, 4), "gpx_s": round(px / (ms / 1e3) / 1e9, 1), "gbs": round(gbs, 1),
+                       "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+        out[str(side)] = r
+        del src, q, dst
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -720,7 +1083,10 @@ def main():
                     help="fixed launch shapes instead of autotuning: "
                          "'WPG,GPC,TW[,XCD[,PC]]:WPG,GPC,TW[,XCD[,PC]]' for the encoder and the "
                          "decoder (PC: cached pixel accesses)")
-    ap.add_argument("--serving-seconds", type=float, default=4.0)
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
+                    help="trace length per rate for the batched and per-request serving modes")
+    ap.add_argument("--serving-aux-seconds", type=float, default=4.0,
+                    help="trace length per rate for the resident and host-payload modes and the burst")
     ap.add_argument("--quality", action="store_true",
                     help="also run the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--legs", default="",
@@ -826,6 +1192,12 @@ def main():
     def want(name):
         return not args.no_extras and (legs is None or name in legs)
 
+    def cpu(name, f, *a):
+        """An oracle timing beside a leg, under cpu_baseline."""
+        if not args.no_cpu:
+            log("cpu baseline (oracle) for %s..." % name)
+            result.setdefault("cpu_baseline", {})[name] = f(*a)
+
     if want("fused_roundtrip"):
         log("fused round-trip leg...")
         ft = None
@@ -841,23 +1213,43 @@ def main():
         torch.cuda.empty_cache()
     del W
     torch.cuda.empty_cache()
+    if want("plain"):
+        log("plain-call leg (one image per call)...")
+        result["plain"] = plain_leg(tdct, torch, stream)
     if want("latency_512"):
         log("latency leg (512 x 512)...")
         result["latency_512"] = latency_leg(tdct, torch, stream)
-    if want("ceiling"):
+        cpu("latency_512", cpu_baseline_512)
+    ceil = {}
+    if want("ceiling") or want("video") or want("batched"):
         log("ceiling leg...")
-        result["ceiling"] = ceiling_leg(tdct, torch, stream)
+        ceil = ceiling_leg(tdct, torch, stream)
+        if want("ceiling"):
+            result["ceiling"] = ceil
     if want("video"):
         log("video leg...")
-        result["video"] = video_leg(tdct, torch, stream)
+        vctx, result["video"] = video_leg(tdct, torch, stream)
+        roof = result["video"]["roofline"]
+        roof["stream_ceiling"] = {"mix": "copy", "gbs": ceil["copy"],
+                                  "frac": round(roof["achieved"] / ceil["copy"], 4)}
         torch.cuda.empty_cache()
+        cpu("video", cpu_baseline_video, vctx)
+        del vctx
     if want("batched"):
         log("batched leg...")
-        result["batched"] = batched_leg(tdct, torch, stream)
+        bctx, result["batched"] = batched_leg(tdct, torch, stream)
+        roof = result["batched"]["roofline"]
+        roof["stream_ceiling"] = {"mix": "read1_write3", "gbs": ceil["read1_write3"],
+                                  "frac": round(roof["achieved"] / ceil["read1_write3"], 4)}
         torch.cuda.empty_cache()
+        cpu("batched", cpu_baseline_ragged, bctx)
+        del bctx
     if want("serving"):
         log("serving leg...")
-        result["serving"] = serving_leg(tdct, torch, args.serving_seconds)
+        result["serving"], sctx = serving_leg(tdct, torch, args.serving_seconds, args.serving_aux_seconds)
+        cpu("serving", cpu_baseline_serving, tdct, torch, sctx, (200, 1000, 5000))
+        del sctx
+        torch.cuda.empty_cache()
     if args.quality:
         log("quality leg...")
         result["quality"] = quality_leg(tdct, torch, stream)

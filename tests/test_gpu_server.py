@@ -271,3 +271,113 @@ def test_resident_large_and_ragged_requests(tdct):
             assert tdct.tdct_server_last_error(srv) == ""
         finally:
             tdct.tdct_server_destroy(srv)
+
+
+# ---- the serving workload at its own request sizes ---------------------------
+# Sides log-uniform multiples of 8 in [32, 8192] with aspect <= 4, encode and
+# decode with p = 1/2, s in {1..8}, payloads windows of 8192^2 planes; plus
+# requests of 32 Mpx and more, so that batches are cut at max_batch_px. Every
+# output is compared with the oracle in full, on the host threads.
+CFG5_SIDE = 8192
+CFG5_THREADS = 16
+
+
+class Cfg5Workload:
+    def __init__(self, tdct, rate=1000.0, seconds=0.12, seed=61):
+        import torch
+        self.planes = [synth.plane(CFG5_SIDE, CFG5_SIDE, 5100 + k) for k in range(2)]
+        # decode inputs: the oracle's encoding of each plane under its own table
+        self.qin = [synth.qtable(1, 2 + 3 * k) for k in range(2)]
+        self.coefs = [O.quantise(p, q, 64, threads=CFG5_THREADS) for p, q in zip(self.planes, self.qin)]
+        self.dplanes = [torch.from_numpy(p).cuda() for p in self.planes]
+        self.dcoefs = [torch.from_numpy(c).cuda() for c in self.coefs]
+        tr = synth.serving_trace(rate, seconds, seed=seed, lo=32, hi=CFG5_SIDE)
+        ops = [int(x) for x in tr["op"]]
+        sides = [(int(w), int(h)) for w, h in zip(tr["w"], tr["h"])]
+        scales = [int(s) for s in tr["s"]]
+        # requests of 32 Mpx and more (the largest the workload draws), one of each op
+        for k, (w, h) in enumerate([(8192, 8192), (8192, 4096), (6144, 6144), (4096, 8192)]):
+            at = (k + 1) * len(ops) // 5
+            ops.insert(at, k % 2)
+            sides.insert(at, (w, h))
+            scales.insert(at, 1 + 2 * k)
+        self.reqs, self.meta = [], []
+        for k, (op, (w, h), s) in enumerate(zip(ops, sides, scales)):
+            p, Q = k % 2, synth.qtable(1, s)
+            keep = 64 if k % 7 else 10
+            if op == 0:
+                r = tdct.request(tdct.OP_ENCODE, w, h, self.dplanes[p], Q, keep=keep, in_stride=CFG5_SIDE)
+            else:
+                r = tdct.request(tdct.OP_DECODE, w, h, self.dcoefs[p], Q)
+            self.reqs.append(r)
+            self.meta.append(dict(op=op, w=w, h=h, p=p, Q=Q, keep=keep))
+        t = np.sort(np.random.default_rng(seed).uniform(0, seconds * 1e6, len(self.reqs)))
+        self.arrival = t.tolist()
+
+    def expected(self, k):
+        m = self.meta[k]
+        w, h = m["w"], m["h"]
+        if m["op"] == 0:
+            q = O.quantise(self.planes[m["p"]][:h], m["Q"], m["keep"], w=w, threads=CFG5_THREADS)
+            return q.view(np.uint8).reshape(-1)
+        nblk = (w // 8) * (h // 8)
+        return O.inverse(self.coefs[m["p"]][:nblk], m["Q"], w, h, threads=CFG5_THREADS).reshape(-1)
+
+
+@pytest.fixture(scope="module")
+def cfg5(tdct):
+    return Cfg5Workload(tdct)
+
+
+def _check_all(W, outs, what):
+    for k in range(len(W.reqs)):
+        assert np.array_equal(outs[k], W.expected(k)), (what, k, W.meta[k]["w"], W.meta[k]["h"])
+
+
+def test_cfg5_sizes_batched_stream_mode_against_oracle(tdct, cfg5):
+    """Continuous batching over 4 streams at the serving workload's own sizes,
+    arriving over 0.12 s, with a 16 Mpx batch cap: every output, the
+    requests of 32 to 64 Mpx included, equals the oracle."""
+    W = cfg5
+    big = [k for k, m in enumerate(W.meta) if m["w"] * m["h"] >= 32 << 20]
+    assert len(big) >= 4 and max(m["w"] for m in W.meta) == CFG5_SIDE
+    budget = 8 << 30
+    cfg = tdct.server_cfg(budget, streams=4, max_batch=64, batching=1, max_batch_px=16 << 20,
+                          tune=dict(pixel_cache=1))
+    outs, lat, st = _serve(tdct, W, cfg)
+    assert st["completed"] == len(W.reqs) and st["failed"] == 0
+    assert st["arena_high_water"] <= budget
+    _check_all(W, outs, "batched")
+
+
+def test_cfg5_sizes_burst_splits_batches_at_the_pixel_cap(tdct, cfg5):
+    """The same requests all at once: batches form and are cut at the 16 Mpx
+    cap (a large request rides alone or with a few small ones), under a budget
+    that makes later requests wait for memory; every output equals the
+    oracle, and equals one plain launch per request."""
+    W = cfg5
+    sizes = [m["w"] * m["h"] * (2 if m["op"] == 0 else 1) for m in W.meta]
+    budget = (max(max(sizes) + 256, sum(sizes) // 3) + 255) // 256 * 256
+    cfg = tdct.server_cfg(budget, streams=4, max_batch=64, batching=1, max_batch_px=16 << 20)
+    hip = _hip()
+    srv = tdct.tdct_server_create(cfg)
+    try:
+        tickets = [tdct.tdct_server_submit(srv, r) for r in W.reqs]
+        res = []
+        for k, t in enumerate(tickets):
+            r = tdct.tdct_server_wait(srv, t)
+            assert r.status == tdct.TDCT_OK, k
+            res.append(r.batch_size)
+            if W.meta[k]["w"] * W.meta[k]["h"] > 16 << 20:
+                assert r.batch_size == 1, k  # above the cap: launched alone
+            got = _read(hip, r.output, r.output_bytes)
+            assert np.array_equal(got, W.expected(k)), ("burst", k)
+            tdct.tdct_server_release(srv, t)
+        st = tdct.tdct_server_stats(srv)
+        assert st["failed"] == 0 and st["arena_high_water"] <= budget
+        assert st["mean_batch"] > 1.0
+    finally:
+        tdct.tdct_server_destroy(srv)
+    per, _, st2 = _serve(tdct, W, tdct.server_cfg(8 << 30, streams=4, max_batch=1, batching=0), arrival=False)
+    assert st2["mean_batch"] == 1.0
+    _check_all(W, per, "per-request")
