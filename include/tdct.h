@@ -215,6 +215,25 @@ void tdct_plan_free(tdct_plan* plan);
 int tdct_run_per_image(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
                        int32_t nq, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work
+ * of tdct_batch_plan + tdct_batch_run in one call, with no plan object and
+ * no allocation. The tables go into a fixed device array of
+ * TDCT_STATIC_TABLE_BYTES (16 MiB) that the library holds on each GPU it
+ * runs on until the process ends: 16 B per tile (128 blocks of encoder-side
+ * work, 64 of decoder or int32-forward work) plus 64 + 768 B per image, each
+ * part rounded up to 256 B. Tables that do not fit return TDCT_ENOMEM before
+ * any device work: about 19,000 images, or 8.6 Gpx of encoding in one call.
+ * Arguments, checks and other errors as for tdct_batch_plan. The tables are
+ * built in host memory of static storage and copied from there, which HIP
+ * performs synchronously with respect to the host; then the kernel is queued
+ * on `stream`. Every call on one GPU shares that GPU's array: calls on one
+ * stream are ordered, but calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. */
+#define TDCT_STATIC_TABLE_BYTES (16 << 20)
+int tdct_batch_run_static(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
+                          int32_t nq, const tdct_tune* tune_or_null, void* stream);
+
 /* ---- serving form ------------------------------------------------------ */
 
 typedef struct {

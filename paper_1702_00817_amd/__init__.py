@@ -122,6 +122,8 @@ _SIG = {
     "tdct_autotune": [_P, _P, _i32, ctypes.POINTER(tdct_tune)],
     "tdct_plan_info_get": [_P, ctypes.POINTER(tdct_plan_info)],
     "tdct_run_per_image": [ctypes.POINTER(tdct_image_desc), _i32, _PQ, _i32, _P],
+    "tdct_batch_run_static": [ctypes.POINTER(tdct_image_desc), _i32, _PQ, _i32,
+                              ctypes.POINTER(tdct_tune), _P],
     "tdct_server_create": [ctypes.POINTER(tdct_server_cfg), ctypes.POINTER(_P)],
     "tdct_server_submit": [_P, ctypes.POINTER(tdct_request), ctypes.POINTER(ctypes.c_uint64)],
     "tdct_server_poll": [_P, ctypes.c_uint64, ctypes.POINTER(tdct_result)],
@@ -310,6 +312,16 @@ def tdct_run_per_image(descs, qtabs, stream=None):
     da, qa = _desc_array(descs), _q_array(qtabs)
     _check(_lib.tdct_run_per_image(da, len(descs), qa, len(qtabs), _stream(stream)),
            "tdct_run_per_image")
+
+
+def tdct_batch_run_static(descs, qtabs, tune=None, stream=None):
+    da, qa = _desc_array(descs), _q_array(qtabs)
+    t = None
+    if tune is not None:
+        t = tdct_tune(**tune) if isinstance(tune, dict) else tune
+    _check(_lib.tdct_batch_run_static(da, len(descs), qa, len(qtabs),
+                                      ctypes.byref(t) if t is not None else None, _stream(stream)),
+           "tdct_batch_run_static")
 
 
 # ---- serving form ------------------------------------------------------------
