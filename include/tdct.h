@@ -343,6 +343,10 @@ int tdct_server_drain(tdct_server* s);
 int tdct_server_stats(tdct_server* s, tdct_stats* out);
 /* Text of the last HIP error the scheduler met ("" if none). */
 const char* tdct_server_last_error(tdct_server* s);
+/* Stops the server: requests in flight finish, requests still waiting for
+ * memory fail, then everything is freed. No other call on the server may
+ * run concurrently with or after it (a thread blocked in tdct_server_wait
+ * must have returned first). */
 void tdct_server_destroy(tdct_server* s);
 
 /* Open-loop replay: request k is submitted at arrival_us[k] after the call

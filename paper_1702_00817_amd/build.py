@@ -8,6 +8,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -40,8 +41,15 @@ def _run(cmd, verbose):
         print(out)
 
 
+def _run_all(cmds, verbose):
+    """Runs independent compile commands side by side (at most 4 at once)."""
+    with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+
+
 def build_lib(verbose: bool = False) -> str:
-    objs = []
+    objs, jobs = [], []
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
@@ -50,8 +58,9 @@ def build_lib(verbose: bool = False) -> str:
         # hipcc compiles .cpp files as HIP too: every source names the target,
         # so no code object for any other GPU is made
         lang = ["-x", "hip"] + DEVICE
-        _run([HIPCC] + COMMON + lang + PER_SOURCE.get(src, []) + ["-c", path, "-o", obj], verbose)
+        jobs.append([HIPCC] + COMMON + lang + PER_SOURCE.get(src, []) + ["-c", path, "-o", obj])
         objs.append(obj)
+    _run_all(jobs, verbose)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs +
          ["-lpthread"], verbose)
@@ -67,6 +76,40 @@ def build_hostcheck(verbose: bool = False) -> str:
     return HOSTCHECK_LIB
 
 
+# Host-only instrumentation: each -fsanitize= applies to the host pass alone
+# (device code is never instrumented), so the sanitizer builds cover the
+# C ABI's host logic -- validation, planning, the server's scheduler and its
+# fake device -- and run on a machine without a GPU.
+SANITIZE = {
+    "address": ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-Xarch_host", "-fno-sanitize-recover=undefined",
+                "-Xarch_host", "-fno-omit-frame-pointer"],
+    "thread": ["-Xarch_host", "-fsanitize=thread"],
+}
+DRIVER_SRC = os.path.join(ROOT, "tests", "sanitize", "fake_device_driver.cpp")
+
+
+def build_sanitized(kind: str, verbose: bool = False) -> str:
+    """Builds the host part of the library's sources and the fake-device
+    driver (tests/sanitize/fake_device_driver.cpp) into one executable
+    instrumented by `kind` ("address": ASan + UBSan, "thread": TSan).
+    Returns the executable's path (under _build/)."""
+    flags = SANITIZE[kind]
+    bdir = os.path.join(PKG, "_build", "sanitize_" + kind)
+    os.makedirs(bdir, exist_ok=True)
+    objs, jobs = [], []
+    for src in SOURCES + [DRIVER_SRC]:
+        path = src if os.path.isabs(src) else os.path.join(CSRC, src)
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        jobs.append([HIPCC] + COMMON + ["-O1", "-g", "-x", "hip"] + DEVICE + flags +
+                    PER_SOURCE.get(src, []) + ["-c", path, "-o", obj])
+        objs.append(obj)
+    _run_all(jobs, verbose)
+    exe = os.path.join(bdir, "fake_device_driver")
+    _run([HIPCC, "--offload-arch=" + ARCH] + flags + ["-o", exe] + objs + ["-lpthread"], verbose)
+    return exe
+
+
 def build(verbose: bool = False) -> str:
     lib = build_lib(verbose)
     build_hostcheck(verbose)
@@ -74,4 +117,7 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(sys.argv[sys.argv.index("--sanitize") + 1], verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
