@@ -786,16 +786,23 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
     return result, {"P": P, "traces": traces, "seconds": seconds, "streams": streams}
 
 
-def _hip_memcpy():
-    """hipMemcpy of the HIP runtime torch loaded (device-to-device copies of
-    arena outputs into torch buffers for the checks)."""
+def _hip_copy_d2d():
+    """A device-to-device copy ordered on torch's current stream (arena
+    outputs into torch buffers for the checks). A plain hipMemcpy between
+    device buffers runs on the null stream and may return before the copy
+    ends, and torch's streams do not wait for the null stream: a comparison
+    queued right after it could read the buffer half copied."""
     import ctypes
 
     import torch
     lib = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
-    lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-    lib.hipMemcpy.restype = ctypes.c_int
-    return lib.hipMemcpy
+    lib.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.c_void_p]
+    lib.hipMemcpyAsync.restype = ctypes.c_int
+
+    def copy(dst, src, nbytes):
+        return lib.hipMemcpyAsync(dst, src, nbytes, 3, torch.cuda.current_stream().cuda_stream)
+    return copy
 
 
 def _oracle_threads():
@@ -840,13 +847,12 @@ def cpu_baseline_serving(tdct, torch, ctx, rates, frac=0.01, big_px=32 << 20, di
     Ed = {k: torch.from_numpy(v).cuda().view(nb, nb, 64) for k, v in E.items()}
     Dd = {k: torch.from_numpy(v).cuda().view(nblk, 8, 8) for k, v in D.items()}
     inputs_ok = all(torch.equal(P["coefs"][p], Ed[(p, 1 + p)].view(nblk, 64)) for p in range(SERVING_POOL))
-    memcpy = _hip_memcpy()
+    copy = _hip_copy_d2d()
     buf = torch.empty(2 * side * side, dtype=torch.uint8, device="cuda")
 
     def matches(tr, k, ptr, nbytes):
         w, h, s_, p = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k]), k % SERVING_POOL
-        torch.cuda.synchronize()
-        assert memcpy(buf.data_ptr(), ptr, nbytes, 3) == 0  # device to device
+        assert copy(buf.data_ptr(), ptr, nbytes) == 0  # ordered before the comparison
         if tr["op"][k] == 0:
             got = buf[:nbytes].view(torch.int16).view(h // 8, w // 8, 64)
             return nbytes == 2 * w * h and torch.equal(got, Ed[(p, s_)][:h // 8, :w // 8])
