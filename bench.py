@@ -786,6 +786,34 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
     return result, {"P": P, "traces": traces, "seconds": seconds, "streams": streams}
 
 
+def burst_leg(tdct, torch, modes, reps=3, seconds=4.0, rate=5000, resident_workers=0):
+    """The serving trace's requests (`seconds` at `rate` req/s) all arriving
+    at once, served `reps` times per mode: capacity of each served form in
+    Gpx/s (wall time from the first submit to the last completion). A short,
+    self-contained run for kernel traces and counters of the served forms."""
+    import synth
+    P = serving_pool(tdct, torch)
+    tr = synth.serving_trace(rate, seconds, seed=5)
+    ra = serving_requests(tdct, tr, P)
+    px = float((tr["w"] * tr["h"]).sum())
+    out = {"requests": len(ra), "gpx": round(px / 1e9, 2)}
+    for mode in modes:
+        runs = []
+        for _ in range(reps):
+            srv = tdct.tdct_server_create(serving_cfg(tdct, mode, resident_workers=resident_workers))
+            try:
+                t0 = time.perf_counter()
+                _, lat, st = tdct.tdct_server_replay(srv, ra, [0.0] * len(ra))
+                wall = time.perf_counter() - t0
+            finally:
+                tdct.tdct_server_destroy(srv)
+            runs.append({"gpx_s": round(px / wall / 1e9, 1), "wall_ms": round(wall * 1e3, 1),
+                         "failed": int(sum(1 for s_ in st if s_ != 0))})
+            log("burst %s: %s" % (mode, json.dumps(runs[-1])))
+        out[mode] = runs
+    return out
+
+
 def _hip_copy_d2d():
     """A device-to-device copy ordered on torch's current stream (arena
     outputs into torch buffers for the checks). A plain hipMemcpy between
@@ -1099,6 +1127,12 @@ def main():
                     help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--fused-tune", default="",
                     help="fixed launch shape 'WPG,GPC,TW[,XCD[,PC]]' for the fused round trip")
+    ap.add_argument("--burst-only", default="",
+                    help="only serve the 5000 req/s trace's requests arriving at once in these "
+                         "comma-separated modes (batched, per_request, resident), for profiling")
+    ap.add_argument("--burst-reps", type=int, default=3)
+    ap.add_argument("--resident-workers", type=int, default=0,
+                    help="worker waves of the resident kernel (0: one per compute unit)")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -1115,6 +1149,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
+
+    if args.burst_only:
+        print(json.dumps({"burst": burst_leg(tdct, torch, args.burst_only.split(","), args.burst_reps,
+                                             resident_workers=args.resident_workers)}), flush=True)
+        return
 
     if args.copy_only:
         # A plain device copy of a known size: the calibration kernel for the

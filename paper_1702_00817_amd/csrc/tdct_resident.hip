@@ -141,13 +141,13 @@ __device__ __forceinline__ void code_item(const ImgDesc& d, const QConst& qc, ui
     uint32_t first = tile0 * tb, count = min(tb, nblk - first);
     if constexpr (OP == OP_ENCODE) {
         EncPixels P;
-        enc_load(d, first, count, lane, P);
+        enc_load<PX_COHERENT>(d, first, count, lane, P);
         for (uint32_t tile = tile0; tile < tile1; ++tile) {
             const bool more = tile + 1 < tile1;
             const uint32_t nfirst = first + tb;
             const uint32_t ncount = more ? min(tb, nblk - nfirst) : 0u;
-            enc_tile<OP_ENCODE>(d, qc, first, count, lane, wl, P, [&]() {
-                if (more) enc_load(d, nfirst, ncount, lane, P);
+            enc_tile<OP_ENCODE, PX_COHERENT>(d, qc, first, count, lane, wl, P, [&]() {
+                if (more) enc_load<PX_COHERENT>(d, nfirst, ncount, lane, P);
             });
             first = nfirst;
             count = ncount;
@@ -159,7 +159,7 @@ __device__ __forceinline__ void code_item(const ImgDesc& d, const QConst& qc, ui
             const bool more = tile + 1 < tile1;
             const uint32_t nfirst = first + tb;
             const uint32_t ncount = more ? min(tb, nblk - nfirst) : 0u;
-            dec_tile(d, qc, first, count, lane, wl, C, [&]() {
+            dec_tile<PX_COHERENT>(d, qc, first, count, lane, wl, C, [&]() {
                 if (more) dec_load(d, nfirst, ncount, lane, C);
             });
             first = nfirst;
@@ -182,6 +182,14 @@ __device__ __forceinline__ uint32_t ticket_state(const ResidentArgs& a, uint64_t
     return pub > t ? 1 : 2;
 }
 
+// Waits until this wave's memory operations have completed; the compiler
+// keeps memory accesses on their side of this point.
+__device__ __forceinline__ void wait_stores() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Items a wave may code before it counts them off (while they belong to the
 // same job and the next item is already published).
 constexpr uint32_t kMaxPendingItems = 8;
@@ -193,17 +201,19 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
     uint32_t pend_slot = 0, pend_items = 0, pend_done = 0;
     auto count_off = [&]() {
         if (pend_items == 0) return;
-        // this wave's outputs before the count; the job's before its flag
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // The tile code wrote this wave's outputs through L2 (PX_COHERENT):
+        // once the stores have completed they are visible device-wide and to
+        // copy engines, so the count needs no L2 write-back, only the wait.
+        wait_stores();
         const uint32_t left = __builtin_amdgcn_readfirstlane(
             __hip_atomic_fetch_add(&a.remaining[pend_slot], lane == 0 ? 0u - pend_items : 0u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT));
         if (left == pend_items) {
-            // every other wave's outputs of the job (released before their
-            // counts), then all of them out to the host
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-            __hip_atomic_store(&a.done[pend_slot], pend_done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            // Every other wave of the job completed its stores before its
+            // count, and this count came after theirs: the job's outputs are
+            // all in memory. The flag itself goes straight to host memory.
+            wait_stores();
+            __hip_atomic_store(&a.done[pend_slot], pend_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
         pend_items = 0;
     };

@@ -48,24 +48,55 @@ __device__ __forceinline__ void st_nt2(void* p, v2u v) {
     __builtin_nontemporal_store(v, reinterpret_cast<v2u*>(p));
 }
 
+// Output stores that write through L2 to memory (agent-scope coherent, sc1)
+// and carry the streaming hint. Each XCD has its own L2, so ordinary stores
+// of one wave become visible to other XCDs and to copy engines only once that
+// L2 is written back; a wave that stores this way makes its outputs visible
+// device-wide as soon as its stores complete (s_waitcnt vmcnt(0)), without
+// writing back the whole L2 of its XCD.
+constexpr int kBufSc1Nt = 16 | 2;              // cache-policy bits: sc1, nt
+constexpr uint32_t kBufRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
+__device__ __forceinline__ void st_wt2(void* p, v2u v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_wt1(uint8_t* p, uint8_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// 16-byte store at base + off (base wave-uniform, off per lane, both in
+// bytes); lanes with off >= limit store nothing.
+__device__ __forceinline__ void st_wt4(void* base, uint32_t off, uint32_t limit, v4u v) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)limit, (int)kBufRsrcWord3);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, kBufSc1Nt);
+}
+
+// Pixel-plane (and output) access policy, a compile-time parameter of the
+// tile code. PX_STREAM and PX_CACHED are the batch kernels' pixel cache
+// policies (below). PX_COHERENT streams loads and writes every output --
+// pixels and coefficients -- through L2 (st_wt*), for kernels whose waves
+// report finished outputs while the kernel keeps running.
+enum { PX_STREAM = 0, PX_CACHED = 1, PX_COHERENT = 2 };
+
 // Pixel-plane accesses under the cache policy a launch picks. Streaming
-// (CACHED false) marks them non-temporal, as above. Cached ones are ordinary
+// (PX_STREAM) marks them non-temporal, as above. Cached ones are ordinary
 // accesses that stay in L2 until evicted: where a tile's pixel rows end
 // inside a 128-byte line (image widths that are not multiples of 128, and
 // tile boundaries inside a row) the neighbouring tile fills the rest of that
 // line, and with both halves meeting in one L2 the line reaches HBM once,
 // whole. Coefficient runs are whole lines and always stream.
-template <bool CACHED>
+template <int PC>
 __device__ __forceinline__ v2u ld_px(const void* p) {
-    if constexpr (CACHED)
+    if constexpr (PC == PX_CACHED)
         return *reinterpret_cast<const v2u*>(p);
     else
         return ld_nt2(p);
 }
-template <bool CACHED>
+template <int PC>
 __device__ __forceinline__ void st_px(void* p, v2u v) {
-    if constexpr (CACHED)
+    if constexpr (PC == PX_CACHED)
         *reinterpret_cast<v2u*>(p) = v;
+    else if constexpr (PC == PX_COHERENT)
+        st_wt2(p, v);
     else
         st_nt2(p, v);
 }
@@ -127,9 +158,10 @@ __device__ __forceinline__ uint32_t swz(uint32_t L) {
 // the run is contiguous; with STRIDE = 2 * CPL it is one half of each of 64
 // blocks of 2 * CPL chunks (an int32 block in two rounds), and every store
 // instruction still writes whole runs of CPL * 16 bytes.
-template <int CPL, int STRIDE = CPL>
+template <int CPL, int STRIDE = CPL, int PC = PX_STREAM>
 __device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint32_t nchunks,
                                           v4u* dst, uint32_t lane) {
+    static_assert(PC != PX_COHERENT || STRIDE == CPL, "coherent stores of contiguous runs only");
 #pragma unroll
     for (int m = 0; m < CPL; ++m) wl[CPL * lane + ((uint32_t)m ^ swz<CPL>(lane))] = mine[m];
     lds_fence();
@@ -142,7 +174,9 @@ __device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint3
         const uint32_t c = 64u * k + lane;
         const uint32_t L = c / CPL, m = c % CPL;
         const v4u v = wl[CPL * L + (m ^ swz<CPL>(L))];
-        if (c < nchunks) {
+        if constexpr (PC == PX_COHERENT)
+            st_wt4(dst, 16u * c, 16u * nchunks, v);  // the range check drops c >= nchunks
+        else if (c < nchunks) {
             if constexpr (STRIDE == CPL)
                 st_nt4(dst + c, v);
             else
@@ -185,13 +219,13 @@ __device__ __forceinline__ void stage_swap(v4u* wl, const v4u (&tmp)[8], uint32_
 
 // ---- pixel side ---------------------------------------------------------------
 
-template <bool CACHED>
+template <int PC>
 __device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int flags,
                                            uint32_t (&R)[8][2]) {
     if (flags & F_SRC8) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const v2u v = ld_px<CACHED>(p + r * stride);
+            const v2u v = ld_px<PC>(p + r * stride);
             R[r][0] = v.x;
             R[r][1] = v.y;
         }
@@ -207,20 +241,25 @@ __device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int
     }
 }
 
-template <bool CACHED>
+template <int PC>
 __device__ __forceinline__ void store_rows8(uint8_t* p, int64_t stride, int flags,
                                             const uint32_t (&R)[8][2]) {
     if (flags & F_DST8) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) st_px<CACHED>(p + r * stride, (v2u){R[r][0], R[r][1]});
+        for (int r = 0; r < 8; ++r) st_px<PC>(p + r * stride, (v2u){R[r][0], R[r][1]});
     } else {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             uint8_t* q = p + r * stride;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                q[c] = (uint8_t)(R[r][0] >> (8 * c));
-                q[4 + c] = (uint8_t)(R[r][1] >> (8 * c));
+                if constexpr (PC == PX_COHERENT) {
+                    st_wt1(q + c, (uint8_t)(R[r][0] >> (8 * c)));
+                    st_wt1(q + 4 + c, (uint8_t)(R[r][1] >> (8 * c)));
+                } else {
+                    q[c] = (uint8_t)(R[r][0] >> (8 * c));
+                    q[4 + c] = (uint8_t)(R[r][1] >> (8 * c));
+                }
             }
         }
     }
@@ -327,7 +366,7 @@ struct EncPixels {
     uint32_t A[8][2], B[8][2];
 };
 
-template <bool CACHED = false>
+template <int PC = PX_STREAM>
 __device__ __forceinline__ void enc_load(const ImgDesc& d, uint32_t first, uint32_t count,
                                          uint32_t lane, EncPixels& P) {
     const bool va = lane < count, vb = lane + 64u < count;
@@ -338,8 +377,8 @@ __device__ __forceinline__ void enc_load(const ImgDesc& d, uint32_t first, uint3
         const uint8_t* pb = d.src + block_offset(d.src_stride, nbx, bb);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const v2u x = ld_px<CACHED>(pa + r * d.src_stride);
-            const v2u y = ld_px<CACHED>(pb + r * d.src_stride);
+            const v2u x = ld_px<PC>(pa + r * d.src_stride);
+            const v2u y = ld_px<PC>(pb + r * d.src_stride);
             P.A[r][0] = x.x;
             P.A[r][1] = x.y;
             P.B[r][0] = y.x;
@@ -349,9 +388,9 @@ __device__ __forceinline__ void enc_load(const ImgDesc& d, uint32_t first, uint3
 #pragma unroll
         for (int r = 0; r < 8; ++r) P.A[r][0] = P.A[r][1] = P.B[r][0] = P.B[r][1] = 0x80808080u;
         if (va)
-            load_rows8<CACHED>(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, P.A);
+            load_rows8<PC>(d.src + block_offset(d.src_stride, nbx, ba), d.src_stride, d.flags, P.A);
         if (vb)
-            load_rows8<CACHED>(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, P.B);
+            load_rows8<PC>(d.src + block_offset(d.src_stride, nbx, bb), d.src_stride, d.flags, P.B);
     }
 }
 
@@ -362,7 +401,7 @@ struct NoPrefetch {
 };
 
 // Codes the tile whose pixels are in P.
-template <int OP, bool CACHED = false, class QC, class PF>
+template <int OP, int PC = PX_STREAM, class QC, class PF>
 __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl, EncPixels& P,
                                          PF&& prefetch) {
@@ -434,8 +473,8 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
             mb[n / 16] = (v4u){wb[0], wb[1], wb[2], wb[3]};
         }
         v4u* out = reinterpret_cast<v4u*>(d.coef) + (int64_t)first * 4;
-        stage_out<4>(wl, ma, 4 * na, out, lane);
-        if (nb) stage_out<4>(wl, mb, 4 * nb, out + 256, lane);
+        stage_out<4, 4, PC>(wl, ma, 4 * na, out, lane);
+        if (nb) stage_out<4, 4, PC>(wl, mb, 4 * nb, out + 256, lane);
     } else if constexpr (OP == OP_ROUNDTRIP_NC) {
         // Encode and decode without storing coefficients. The rounding float
         // t is M + q exactly (an integer in [2^23, 2^24)), so t - M is q as an
@@ -448,7 +487,7 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
                 W[k] = (__builtin_bit_cast(float, quant_bits(v[k].x, qc.r[k])) - kRoundMagic) *
                        qc.qs[k];
             reconstruct_f(W, px);
-            store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+            store_rows8<PC>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
         }
         if (vb) {
             float W[64];
@@ -457,7 +496,7 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
                 W[k] = (__builtin_bit_cast(float, quant_bits(v[k].y, qc.r[k])) - kRoundMagic) *
                        qc.qs[k];
             reconstruct_f(W, px);
-            store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
+            store_rows8<PC>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
         }
     } else {
         // OP_ENCODE / OP_ROUNDTRIP: int16 coefficients, natural order.
@@ -473,34 +512,34 @@ __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_
             v4u m8[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) m8[m] = (v4u){qa[4 * m], qa[4 * m + 1], qa[4 * m + 2], qa[4 * m + 3]};
-            stage_out<8>(wl, m8, 8 * na, out, lane);
+            stage_out<8, 8, PC>(wl, m8, 8 * na, out, lane);
             if (nb) {
 #pragma unroll
                 for (int m = 0; m < 8; ++m)
                     m8[m] = (v4u){qb[4 * m], qb[4 * m + 1], qb[4 * m + 2], qb[4 * m + 3]};
-                stage_out<8>(wl, m8, 8 * nb, out + 512, lane);
+                stage_out<8, 8, PC>(wl, m8, 8 * nb, out + 512, lane);
             }
         }
         if constexpr (OP == OP_ROUNDTRIP) {
             uint32_t px[8][2];
             if (va) {
                 decode_block_rt(qa, qc, px);
-                store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
+                store_rows8<PC>(d.dst + block_offset(d.dst_stride, nbx, ba), d.dst_stride, d.flags, px);
             }
             if (vb) {
                 decode_block_rt(qb, qc, px);
-                store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
+                store_rows8<PC>(d.dst + block_offset(d.dst_stride, nbx, bb), d.dst_stride, d.flags, px);
             }
         }
     }
 }
 
-template <int OP, bool CACHED = false, class QC>
+template <int OP, int PC = PX_STREAM, class QC>
 __device__ __forceinline__ void enc_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl) {
     EncPixels P;
-    enc_load<CACHED>(d, first, count, lane, P);
-    enc_tile<OP, CACHED>(d, qc, first, count, lane, wl, P, NoPrefetch());
+    enc_load<PC>(d, first, count, lane, P);
+    enc_tile<OP, PC>(d, qc, first, count, lane, wl, P, NoPrefetch());
 }
 
 // ---- decoder tile -----------------------------------------------------------
@@ -519,7 +558,7 @@ __device__ __forceinline__ void dec_load(const ImgDesc& d, uint32_t first, uint3
 }
 
 // Decodes lane's block from its 8 chunks and stores its pixels.
-template <bool CACHED = false, class QC>
+template <int PC = PX_STREAM, class QC>
 __device__ __forceinline__ void dec_finish(const ImgDesc& d, const QC& qc, uint32_t first,
                                            uint32_t lane, const v4u (&mine)[8]) {
     uint32_t qp[32];
@@ -533,11 +572,11 @@ __device__ __forceinline__ void dec_finish(const ImgDesc& d, const QC& qc, uint3
     uint32_t px[8][2];
     decode_block(qp, qc, px);
     const uint32_t b = first + lane;
-    store_rows8<CACHED>(d.dst + block_offset(d.dst_stride, (uint32_t)d.nbx, b), d.dst_stride, d.flags,
+    store_rows8<PC>(d.dst + block_offset(d.dst_stride, (uint32_t)d.nbx, b), d.dst_stride, d.flags,
                         px);
 }
 
-template <class QC, class PF>
+template <int PC = PX_STREAM, class QC, class PF>
 __device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl, DecChunks& C,
                                          PF&& prefetch) {
@@ -545,26 +584,26 @@ __device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_
     stage_swap(wl, C.c, lane, mine);
     prefetch();
     if (lane >= count) return;
-    dec_finish(d, qc, first, lane, mine);
+    dec_finish<PC>(d, qc, first, lane, mine);
 }
 
-template <bool CACHED = false, class QC>
+template <int PC = PX_STREAM, class QC>
 __device__ __forceinline__ void dec_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl) {
     v4u tmp[8], mine[8];
     stage_load(reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, tmp);
     stage_swap(wl, tmp, lane, mine);
     if (lane >= count) return;
-    dec_finish<CACHED>(d, qc, first, lane, mine);
+    dec_finish<PC>(d, qc, first, lane, mine);
 }
 
-template <int OP, bool CACHED = false, class QC>
+template <int OP, int PC = PX_STREAM, class QC>
 __device__ __forceinline__ void run_tile(const ImgDesc& d, const QC& qc, uint32_t first,
                                          uint32_t count, uint32_t lane, v4u* wl) {
     if constexpr (OP == OP_DECODE)
-        dec_tile<CACHED>(d, qc, first, count, lane, wl);
+        dec_tile<PC>(d, qc, first, count, lane, wl);
     else
-        enc_tile<OP, CACHED>(d, qc, first, count, lane, wl);
+        enc_tile<OP, PC>(d, qc, first, count, lane, wl);
 }
 
 // LDS bytes one wave needs for a set of ops (bit i = op i).
