@@ -782,7 +782,7 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
     result = {"seconds_per_rate": {"batched": seconds, "per_request": seconds, "resident": aux_seconds,
                                    "host_io_batched": aux_seconds},
               "streams": streams, "budget_gb": 64,
-              "resident_workers": resident_workers or "one per CU", "rates": out}
+              "resident_workers": resident_workers or "four per CU", "rates": out}
     return result, {"P": P, "traces": traces, "seconds": seconds, "streams": streams}
 
 
@@ -1132,7 +1132,7 @@ def main():
                          "comma-separated modes (batched, per_request, resident), for profiling")
     ap.add_argument("--burst-reps", type=int, default=3)
     ap.add_argument("--resident-workers", type=int, default=0,
-                    help="worker waves of the resident kernel (0: one per compute unit)")
+                    help="worker waves of the resident kernel (0: four per compute unit)")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

@@ -202,10 +202,38 @@ int tdct_batch_graph(tdct_plan* plan, void* stream);
 /* Times candidate launch shapes on the plan (reps launches each, after one
  * warm-up), then times the four fastest again in turn over max(5, reps)
  * rounds or more (up to 25, about 0.2 s of launches), keeps the one with the
- * lowest median in the plan and returns it in *best. Outputs are overwritten
+ * lowest median in the plan and returns it in *best. With the autotune cache
+ * on (below), a shape stored for the plan's class is applied instead, with no
+ * launch, and a newly timed winner is stored. Outputs are overwritten
  * with the same bytes by every candidate (a plan's outputs never overlap its
  * inputs, see tdct_batch_plan). */
 int tdct_autotune(tdct_plan* plan, void* stream, int32_t reps, tdct_tune* best);
+
+/* Autotune cache (process-wide). tdct_tune_cache_open(path) loads the JSON
+ * file at `path` (a missing file is an empty cache; NULL or "" turns the
+ * cache off; TDCT_EINVAL, cache off, for a file not in the cache's format)
+ * and replaces the environment's choice: without a call, the first use of the
+ * cache opens the file named by $TDCT_TUNE_CACHE, if set. While the cache is
+ * on, tdct_autotune first looks up the plan's class -- device architecture,
+ * the library's source hash, op set, size class floor(log2(tiles)) and
+ * whether every pixel plane's
+ * address, width and stride are multiples of 128 bytes -- and on a hit applies
+ * the stored shape without timing anything; on a miss it times candidates as
+ * below and stores the winner, rewriting the file (through a temporary file
+ * and a rename). Servers created with tune_cache = 1 launch each batch in the
+ * shape stored for its class, or for the nearest size class within a factor
+ * of 4 (tdct_server_cfg). The file holds one object:
+ * {"format": "tdct-autotune-1", "entries": {"gfx950/src=<hash>/ops=1/tiles=17/aligned=1":
+ * [waves_per_group, groups_per_cu, tile_waves, xcd_remap, pixel_cache], ...}}.
+ * Write failures leave the file as it was and are counted. */
+typedef struct {
+    int32_t on;       /* 1 while a cache file is open */
+    int32_t reserved;
+    int64_t entries;  /* classes held */
+    int64_t hits, misses, stores, write_errors; /* since the cache was opened */
+} tdct_tune_cache_stats;
+int tdct_tune_cache_open(const char* path);
+int tdct_tune_cache_info(tdct_tune_cache_stats* out);
 
 int tdct_plan_info_get(const tdct_plan* plan, tdct_plan_info* out);
 void tdct_plan_free(tdct_plan* plan);
@@ -275,7 +303,7 @@ typedef struct {
      * requests are refused (TDCT_EINVAL). With fake_device_us > 0 a host
      * thread plays the kernel's part of the protocol. */
     int32_t resident;
-    int32_t resident_workers; /* worker waves (0: one per compute unit; clamped to what
+    int32_t resident_workers; /* worker waves (0: four per compute unit; clamped to what
                                  fits on the device at once) */
     int32_t resident_idle_us; /* 0: 20000 */
     int32_t resident_jobs;    /* queue slots, rounded up to a power of two (0: 1024,
@@ -286,6 +314,10 @@ typedef struct {
                                  decoding; an item holds one or more tiles) is
                                  refused with TDCT_ENOMEM */
     int32_t resident_reserved;
+    int32_t tune_cache;       /* 1: each batch launch takes the autotune cache's shape for
+                                 its class (nearest size class within a factor of 4), when
+                                 the cache holds one; otherwise `tune` */
+    int32_t reserved2;
 } tdct_server_cfg;
 
 typedef struct {

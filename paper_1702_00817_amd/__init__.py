@@ -76,7 +76,14 @@ class tdct_server_cfg(ctypes.Structure):
                 ("fake_device_us", ctypes.c_int32), ("fake_fail_every", ctypes.c_int32),
                 ("resident", ctypes.c_int32), ("resident_workers", ctypes.c_int32),
                 ("resident_idle_us", ctypes.c_int32), ("resident_jobs", ctypes.c_int32),
-                ("resident_tiles", ctypes.c_int32), ("resident_reserved", ctypes.c_int32)]
+                ("resident_tiles", ctypes.c_int32), ("resident_reserved", ctypes.c_int32),
+                ("tune_cache", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+
+
+class tdct_tune_cache_stats(ctypes.Structure):
+    _fields_ = [("on", ctypes.c_int32), ("reserved", ctypes.c_int32), ("entries", ctypes.c_int64),
+                ("hits", ctypes.c_int64), ("misses", ctypes.c_int64), ("stores", ctypes.c_int64),
+                ("write_errors", ctypes.c_int64)]
 
 
 class tdct_request(ctypes.Structure):
@@ -121,6 +128,8 @@ _SIG = {
     "tdct_batch_graph": [_P, _P],
     "tdct_autotune": [_P, _P, _i32, ctypes.POINTER(tdct_tune)],
     "tdct_plan_info_get": [_P, ctypes.POINTER(tdct_plan_info)],
+    "tdct_tune_cache_open": [ctypes.c_char_p],
+    "tdct_tune_cache_info": [ctypes.POINTER(tdct_tune_cache_stats)],
     "tdct_run_per_image": [ctypes.POINTER(tdct_image_desc), _i32, _PQ, _i32, _P],
     "tdct_batch_run_static": [ctypes.POINTER(tdct_image_desc), _i32, _PQ, _i32,
                               ctypes.POINTER(tdct_tune), _P],
@@ -297,6 +306,17 @@ def tdct_autotune(plan, stream=None, reps=3) -> dict:
     return t.as_dict()
 
 
+def tdct_tune_cache_open(path):
+    """Opens the autotune cache file at `path` (None or "": cache off)."""
+    _check(_lib.tdct_tune_cache_open(os.fsencode(path) if path else None), "tdct_tune_cache_open")
+
+
+def tdct_tune_cache_info() -> dict:
+    st = tdct_tune_cache_stats()
+    _check(_lib.tdct_tune_cache_info(ctypes.byref(st)), "tdct_tune_cache_info")
+    return {k: getattr(st, k) for k in ("on", "entries", "hits", "misses", "stores", "write_errors")}
+
+
 def tdct_plan_info_get(plan) -> dict:
     i = tdct_plan_info()
     _check(_lib.tdct_plan_info_get(plan, ctypes.byref(i)), "tdct_plan_info_get")
@@ -328,7 +348,7 @@ def tdct_batch_run_static(descs, qtabs, tune=None, stream=None):
 
 def server_cfg(budget_bytes, streams=4, max_batch=64, max_wait_us=0, batching=1, tune=None,
                fake_device_us=0, fake_fail_every=0, max_batch_px=0, resident=0, resident_workers=0,
-               resident_idle_us=0, resident_jobs=0, resident_tiles=0) -> tdct_server_cfg:
+               resident_idle_us=0, resident_jobs=0, resident_tiles=0, tune_cache=0) -> tdct_server_cfg:
     c = tdct_server_cfg()
     c.budget_bytes, c.streams, c.max_batch = budget_bytes, streams, max_batch
     c.max_wait_us, c.batching, c.max_batch_px = max_wait_us, batching, max_batch_px
@@ -337,6 +357,7 @@ def server_cfg(budget_bytes, streams=4, max_batch=64, max_wait_us=0, batching=1,
     c.fake_device_us, c.fake_fail_every = fake_device_us, fake_fail_every
     c.resident, c.resident_workers, c.resident_idle_us = resident, resident_workers, resident_idle_us
     c.resident_jobs, c.resident_tiles = resident_jobs, resident_tiles
+    c.tune_cache = tune_cache
     return c
 
 

@@ -19,7 +19,7 @@ HOSTCHECK_SRC = os.path.join(ROOT, "tests", "hostcheck.cpp")
 HOSTCHECK_LIB = os.path.join(ROOT, "tests", "libhostcheck.so")
 
 SOURCES = ["tdct_kernels.hip", "tdct_probe.hip", "tdct_resident.hip", "tdct_static.hip",
-           "tdct_batch.cpp", "tdct_server.cpp"]
+           "tdct_batch.cpp", "tdct_server.cpp", "tdct_tunecache.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
@@ -41,6 +41,22 @@ def _run(cmd, verbose):
         print(out)
 
 
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over the library's sources and
+    header: built into the library, it keys the autotune cache, so shapes
+    tuned for other kernel code are never taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".cpp", ".hpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    with open(os.path.join(INCLUDE, "tdct.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _run_all(cmds, verbose):
     """Runs independent compile commands side by side (at most 4 at once)."""
     with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
@@ -52,13 +68,14 @@ def build_lib(verbose: bool = False) -> str:
     objs, jobs = [], []
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
+    ident = ['-DTDCT_SOURCE_HASH="%s"' % source_hash()]
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(bdir, src + ".o")
         # hipcc compiles .cpp files as HIP too: every source names the target,
         # so no code object for any other GPU is made
         lang = ["-x", "hip"] + DEVICE
-        jobs.append([HIPCC] + COMMON + lang + PER_SOURCE.get(src, []) + ["-c", path, "-o", obj])
+        jobs.append([HIPCC] + COMMON + ident + lang + PER_SOURCE.get(src, []) + ["-c", path, "-o", obj])
         objs.append(obj)
     _run_all(jobs, verbose)
     tmp = LIB + ".tmp%d" % os.getpid()

@@ -354,6 +354,18 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
             if (best) *best = p->tune;
             return TDCT_OK;
         }
+        // a shape stored for the plan's class: applied without timing
+        std::string arch, key;
+        int st0 = device_arch(&arch);
+        if (st0) return st0;
+        key = tune_key(arch, p->ops, (int64_t)p->tiles.size(), pixels_aligned(p->imgs.data(), p->imgs.size()));
+        tdct_tune cached;
+        if (tune_cache_get(key, &cached)) {
+            free_graph(p);  // a captured graph holds the launch shape it was made with
+            p->tune = cached;
+            if (best) *best = cached;
+            return TDCT_OK;
+        }
         hipStream_t s = (hipStream_t)stream;
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return TDCT_EDEVICE;
@@ -458,6 +470,7 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
         free_graph(p);  // a captured graph holds the launch shape it was made with
         p->tune = winner;
         if (best) *best = winner;
+        tune_cache_put(key, winner);
         return TDCT_OK;
     });
 }

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <new>
+#include <string>
 
 #include "tdct.h"
 #include "tdct_device.hpp"
@@ -72,10 +73,22 @@ int launch_batch(const Tile* tiles, const ImgDesc* imgs, const QConst* qcs, uint
 // LDS bytes per workgroup of the batch kernel for an op set and launch shape.
 uint32_t batch_lds_bytes(int ops, int waves_per_group);
 
+// Autotune cache (tdct_tunecache.cpp): the device's architecture name
+// (gfx950), whether every pixel plane of a batch is 128-byte aligned in
+// address, width and stride, a batch's class key, and lookups and stores
+// (no-ops while the cache is off).
+int device_arch(std::string* out);
+bool pixels_aligned(const ImgDesc* imgs, size_t n);
+std::string tune_key(const std::string& arch, int ops, int64_t tiles, bool aligned);
+bool tune_cache_get(const std::string& key, tdct_tune* out);
+bool tune_cache_nearest(const std::string& arch, int ops, int64_t tiles, bool aligned, tdct_tune* out);
+void tune_cache_put(const std::string& key, const tdct_tune& t);
+
 struct ResidentArgs;
 // Workgroups of the resident kernel that fit on the device at once.
 int resident_capacity(int num_cus, int* groups);
-// One front wave plus `workers` worker waves.
-int launch_resident(const ResidentArgs& a, int workers, hipStream_t stream);
+// One front wave plus `workers` worker waves, after rewinding the ticket
+// cursors when `rewind` (every launch but the first).
+int launch_resident(const ResidentArgs& a, int workers, bool rewind, hipStream_t stream);
 
 }  // namespace tdct

@@ -96,9 +96,20 @@ __device__ void front_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0) {
             // the host wrote these jobs before raising the count
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
             const uint32_t n = pub - taken < kIngestBatch ? (uint32_t)(pub - taken) : kIngestBatch;
-            // items published and not yet handed out (negative while workers wait)
-            const uint64_t handed =
-                first_lane64(__hip_atomic_load(&a.st->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            // items published and not yet handed out (negative while workers
+            // wait): the tickets of all queues, one cursor per lane, summed
+            // across the wave
+            const uint32_t cq = lane < a.nq ? lane : a.nq - 1;
+            uint64_t mine = __hip_atomic_load(&a.cursors[cq * kCursorStride], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+            mine = lane < a.nq ? mine : 0;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)mine, off);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(mine >> 32), off);
+                mine += ((uint64_t)hi << 32) | lo;
+            }
+            const uint64_t handed = first_lane64(mine);
             for (uint32_t j = 0; j < n; ++j) {
                 const uint32_t slot = (uint32_t)(taken + j) & jmask;
                 v4u c = reinterpret_cast<const v4u*>(a.ring + slot)[k];
@@ -110,7 +121,10 @@ __device__ void front_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0) {
                 c.x = k == kCountChunk ? (uint32_t)items : (k == kItemChunk ? per : c.x);
                 c.y = k == kCountChunk ? (uint32_t)(items >> 32) : c.y;
                 reinterpret_cast<v4u*>(a.jobs + slot)[k] = c;
-                a.remaining[slot] = nitems;
+                // lanes past the last queue repeat its store (same value, same place)
+                const uint32_t q = lane < a.nq ? lane : a.nq - 1;
+                a.remaining[remaining_at(q, slot, a.ring_jobs)] = items_in_queue(items, nitems, q, a.nq);
+                a.remaining[queues_left_at(slot, a.ring_jobs)] = nitems < a.nq ? nitems : a.nq;
                 for (uint32_t i = lane; i < nitems; i += 64) a.item_slot[(uint32_t)(items + i) & imask] = slot;
                 items += nitems;
             }
@@ -194,8 +208,11 @@ __device__ __forceinline__ void wait_stores() {
 // same job and the next item is already published).
 constexpr uint32_t kMaxPendingItems = 8;
 
-__device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v4u* wl, v4u* jl) {
+__device__ void worker_wave(const ResidentArgs& a, uint32_t worker, uint32_t lane, uint64_t t0, v4u* wl,
+                            v4u* jl) {
     const uint32_t imask = a.ring_items - 1;
+    const uint32_t queue = worker & (a.nq - 1);
+    uint64_t* const cursor = &a.cursors[queue * kCursorStride];
     const uint32_t k = lane < (uint32_t)kJobChunks ? lane : (uint32_t)kJobChunks - 1;
     // Items coded and not yet counted off, all of the job in pend_slot.
     uint32_t pend_slot = 0, pend_items = 0, pend_done = 0;
@@ -205,10 +222,16 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
         // once the stores have completed they are visible device-wide and to
         // copy engines, so the count needs no L2 write-back, only the wait.
         wait_stores();
-        const uint32_t left = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_fetch_add(&a.remaining[pend_slot], lane == 0 ? 0u - pend_items : 0u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT));
-        if (left == pend_items) {
+        const uint32_t left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+            &a.remaining[remaining_at(queue, pend_slot, a.ring_jobs)], lane == 0 ? 0u - pend_items : 0u,
+            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        // the job's items of this queue are all coded: count the queue off
+        const uint32_t queues = left != pend_items
+                                    ? 0u
+                                    : __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+                                          &a.remaining[queues_left_at(pend_slot, a.ring_jobs)],
+                                          lane == 0 ? 0xffffffffu : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (queues == 1) {
             // Every other wave of the job completed its stores before its
             // count, and this count came after theirs: the job's outputs are
             // all in memory. The flag itself goes straight to host memory.
@@ -224,13 +247,15 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t lane, uint64_t t0, v
     uint32_t ntiles = 0, per = 1, tb = kEncTileBlocks, done_value = 0, slot = 0;
     const ResidentJob* J = reinterpret_cast<const ResidentJob*>(jl);
     while (true) {
-        // A ticket is the index of the next work item this wave codes; taking
-        // one always succeeds, and the wave then waits for that item to be
-        // published. A wave that leaves holding an unpublished ticket loses
-        // it: before a relaunch the host rewinds the cursor to the published
-        // count, which is where the first lost ticket starts.
-        const uint64_t t = first_lane64(__hip_atomic_fetch_add(&a.st->cursor, lane == 0 ? 1ull : 0ull,
-                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        // A ticket of this wave's queue names the next work item it codes
+        // (ticket k of queue q is item k nq + q); taking one always succeeds,
+        // and the wave then waits for that item to be published. A wave that
+        // leaves holding an unpublished ticket loses it: before a relaunch
+        // each cursor is rewound to its queue's first unpublished item.
+        const uint64_t t = first_lane64(__hip_atomic_fetch_add(cursor, lane == 0 ? 1ull : 0ull, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT)) *
+                               a.nq +
+                           queue;
         uint64_t pub;
         uint32_t state = ticket_state(a, t, t0, pub);
         if (state != 1) {
@@ -291,7 +316,20 @@ __global__ __launch_bounds__(64) void resident_kernel(const ResidentArgs a) {
     if (blockIdx.x == 0)
         front_wave(a, lane, t0);
     else
-        worker_wave(a, lane, t0, lds, lds + kResidentStageBytes / 16);
+        worker_wave(a, blockIdx.x - 1, lane, t0, lds, lds + kResidentStageBytes / 16);
+}
+
+// Before a relaunch, on the kernel's stream (so after the previous launch
+// has ended): each queue's cursor goes back to its first item not yet
+// published (tickets the exiting workers took beyond the published items
+// were lost), or stays if it is behind that.
+__global__ void resident_rewind(const ResidentArgs a) {
+    const uint32_t q = threadIdx.x;
+    if (q >= a.nq) return;
+    const uint64_t pub = a.st->items_pub;
+    const uint64_t first = pub > q ? (pub - q + a.nq - 1) / a.nq : 0;
+    uint64_t* c = &a.cursors[q * kCursorStride];
+    *c = *c < first ? *c : first;
 }
 
 }  // namespace
@@ -309,7 +347,12 @@ int resident_capacity(int num_cus, int* groups) {
     return TDCT_OK;
 }
 
-int launch_resident(const ResidentArgs& a, int workers, hipStream_t stream) {
+int launch_resident(const ResidentArgs& a, int workers, bool rewind, hipStream_t stream) {
+    if (rewind) {
+        hipLaunchKernelGGL(resident_rewind, dim3(1), dim3(64), 0, stream, a);
+        const int st = check_launch("resident cursor rewind");
+        if (st) return st;
+    }
     hipLaunchKernelGGL(resident_kernel, dim3(1 + workers), dim3(64), kResidentLdsBytes, stream, a);
     return check_launch("resident kernel launch");
 }

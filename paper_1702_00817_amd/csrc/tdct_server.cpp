@@ -139,7 +139,7 @@ struct Resident {
     uint64_t* ctrl = nullptr;
     ResidentJob* ring = nullptr;
     uint32_t* done = nullptr;
-    void* dev = nullptr;  // state | remaining | job copies | tile ring
+    void* dev = nullptr;  // state | cursors | completion counters | job copies | item ring
     ResidentArgs args{};
     uint32_t epoch = 0;
     bool running = false;  // a launch may still be on the device
@@ -167,6 +167,7 @@ struct tdct_server {
     tdct_server_cfg cfg{};
     bool fake = false;
     int num_cus = 0;
+    std::string arch;  // device architecture (autotune cache keys)
     Arena* arena = nullptr;
     char* arena_base = nullptr;
     std::mutex mu;
@@ -386,8 +387,14 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
             return TDCT_EDEVICE;
         }
         char* dbase = (char*)sl.dev;
+        // the autotune cache's shape for this batch's class, if asked for
+        // and stored
+        tdct_tune tune = s->cfg.tune;
+        if (s->cfg.tune_cache)
+            (void)tune_cache_nearest(s->arch, ops, (int64_t)tiles.size(),
+                                     pixels_aligned(imgs.data(), imgs.size()), &tune);
         st = launch_batch((const Tile*)dbase, (const ImgDesc*)(dbase + tb),
-                          (const QConst*)(dbase + tb + ib), (uint32_t)tiles.size(), ops, s->cfg.tune,
+                          (const QConst*)(dbase + tb + ib), (uint32_t)tiles.size(), ops, tune,
                           s->num_cus, sl.stream);
         if (st) return st;
     }
@@ -663,13 +670,15 @@ int resident_init(tdct_server* s) {
     }
     int st = resident_capacity(s->num_cus, &groups);
     if (st) return st;
-    R.workers = c.resident_workers > 0 ? c.resident_workers : s->num_cus;
+    // four worker waves per CU by default: one per SIMD
+    R.workers = c.resident_workers > 0 ? c.resident_workers : 4 * s->num_cus;
     R.workers = std::min(R.workers, groups - 1);
     if (R.workers < 1) return TDCT_EDEVICE;
     void* hdev = nullptr;
     e = hipHostGetDevicePointer(&hdev, R.host, 0);
-    const size_t rem_off = sizeof(ResidentState);
-    const size_t jobs_off = (rem_off + (size_t)R.ring_jobs * 4 + 255) & ~size_t(255);
+    const size_t cur_off = sizeof(ResidentState);
+    const size_t rem_off = cur_off + kMaxQueues * kCursorStride * sizeof(uint64_t);
+    const size_t jobs_off = (rem_off + (size_t)counter_words(R.ring_jobs) * 4 + 255) & ~size_t(255);
     const size_t slot_off = jobs_off + (size_t)R.ring_jobs * sizeof(ResidentJob);
     const size_t dev_bytes = slot_off + (size_t)R.ring_tiles * 4;
     if (e == hipSuccess) e = hipMalloc(&R.dev, dev_bytes);
@@ -689,12 +698,14 @@ int resident_init(tdct_server* s) {
     a.ring = (const ResidentJob*)(hd + ring_off);
     a.done = (uint32_t*)(hd + done_off);
     a.st = (ResidentState*)d;
+    a.cursors = (uint64_t*)(d + cur_off);
     a.remaining = (uint32_t*)(d + rem_off);
     a.jobs = (ResidentJob*)(d + jobs_off);
     a.item_slot = (uint32_t*)(d + slot_off);
     a.ring_jobs = R.ring_jobs;
     a.ring_items = R.ring_tiles;
     a.workers = (uint32_t)R.workers;
+    a.nq = resident_queues(a.workers);
     a.idle_ticks = (uint64_t)(R.idle_us * (double)khz / 1000.0);
     a.life_ticks = (uint64_t)(kLifeUs * (double)khz / 1000.0);
     return TDCT_OK;
@@ -724,17 +735,10 @@ int resident_enqueue(tdct_server* s) {
     R.epoch++;
     s->batches++;
     R.args.epoch = R.epoch;
-    if (R.epoch > 1) {
-        // Tickets the last launch's workers left with are beyond its last
-        // published work item; start handing out tickets from there again.
-        hipError_t e = hipMemcpyAsync(&R.args.st->cursor, &R.args.st->items_pub, sizeof(uint64_t),
-                                      hipMemcpyDeviceToDevice, R.stream);
-        if (e != hipSuccess) {
-            set_error("resident cursor rewind", e);
-            return TDCT_EDEVICE;
-        }
-    }
-    return launch_resident(R.args, R.workers, R.stream);
+    // Tickets the last launch's workers left with are beyond its last
+    // published work item; each queue hands out tickets from its first
+    // unpublished item again.
+    return launch_resident(R.args, R.workers, R.epoch > 1, R.stream);
 }
 
 // Starts the kernel (or its host stand-in) when no launch is live. Lock held.
@@ -1007,6 +1011,8 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
             hipError_t e = hipGetDevice(&dev);
             if (e == hipSuccess)
                 e = hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e == hipSuccess && cfg->tune_cache && device_arch(&s->arch) != TDCT_OK)
+                return TDCT_EDEVICE;
             if (e == hipSuccess &&
                 (e = hipMalloc((void**)&s->arena_base, (size_t)cfg->budget_bytes)) != hipSuccess)
                 s->arena_base = nullptr;

@@ -106,6 +106,44 @@ def test_plans_refuse_outputs_over_inputs(tdct):
         L.tdct_plan_free(h)
 
 
+def test_tune_cache_file_format(tdct, tmp_path):
+    """The autotune cache opens a missing file as empty, reads the file
+    format it writes, and refuses anything else (cache off). Lookups and
+    stores need a device (GPU tests)."""
+    path = str(tmp_path / "tune.json")
+    try:
+        tdct.tdct_tune_cache_open(path)
+        info = tdct.tdct_tune_cache_info()
+        assert info["on"] == 1 and info["entries"] == 0
+        good = ('{"format": "tdct-autotune-1", "entries": {\n'
+                '  "gfx950/src=0123456789abcdef/ops=1/tiles=17/aligned=1": [4, 1, 2, 1, 0],\n'
+                '  "gfx950/src=0123456789abcdef/ops=2/tiles=18/aligned=1": [2, 4096, 1, 0, 1]\n}}\n')
+        open(path, "w").write(good)
+        tdct.tdct_tune_cache_open(path)
+        assert tdct.tdct_tune_cache_info()["entries"] == 2
+        open(path, "w").write('{"format": "tdct-autotune-1", "entries": {}}')
+        tdct.tdct_tune_cache_open(path)
+        assert tdct.tdct_tune_cache_info() ["entries"] == 0
+        bad = [good.replace("[4, 1, 2", "[3, 1, 2"),           # waves per group not 1/2/4/8
+               good.replace("[2, 4096, 1, 0, 1]", "[2, 4096, 1, 0]"),  # a field missing
+               good.replace("tdct-autotune-1", "tdct-autotune-0"),
+               good.replace('"entries"', '"entry"'),
+               good[:-3],                                          # truncated
+               good + "x",                                         # trailing bytes
+               "[]"]
+        for text in bad:
+            open(path, "w").write(text)
+            with pytest.raises(tdct.TdctError) as e:
+                tdct.tdct_tune_cache_open(path)
+            assert e.value.status == tdct.TDCT_EINVAL
+            assert tdct.tdct_tune_cache_info()["on"] == 0
+        tdct.tdct_tune_cache_open(path + ".missing")
+        assert tdct.tdct_tune_cache_info()["on"] == 1
+    finally:
+        tdct.tdct_tune_cache_open(None)
+    assert tdct.tdct_tune_cache_info()["on"] == 0
+
+
 # ---- server logic on the fake device ----------------------------------------
 
 def test_server_tune_is_validated(tdct):

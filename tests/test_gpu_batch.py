@@ -241,6 +241,54 @@ def test_autotuner_result_and_per_image_launches(tdct):
         tdct.tdct_plan_free(plan)
 
 
+def test_autotune_cache_skips_the_search_and_keeps_the_shape(tdct, tmp_path):
+    """With the autotune cache on, the first autotune of a class times
+    candidates and stores the winner in the file; a new process (here: the
+    file opened again) applies the stored shape to another plan of the same
+    class without timing anything, and that plan's outputs are the oracle's.
+    A plan of another class misses."""
+    import time
+    path = str(tmp_path / "tune.json")
+    try:
+        tdct.tdct_tune_cache_open(path)
+        A = Ragged(tdct, seed=21)
+        pa = tdct.tdct_batch_plan(A.descs, A.qtabs)
+        try:
+            best = tdct.tdct_autotune(pa, reps=1)
+        finally:
+            tdct.tdct_plan_free(pa)
+        info = tdct.tdct_tune_cache_info()
+        assert info["stores"] == 1 and info["entries"] == 1 and info["misses"] == 1
+        text = open(path).read()
+        assert '"format": "tdct-autotune-1"' in text and "/ops=" in text
+        tdct.tdct_tune_cache_open(path)  # as a later process would
+        B = Ragged(tdct, seed=21)  # same sizes and ops, new buffers
+        pb = tdct.tdct_batch_plan(B.descs, B.qtabs)
+        try:
+            t0 = time.perf_counter()
+            again = tdct.tdct_autotune(pb, reps=1)
+            assert time.perf_counter() - t0 < 0.05  # no candidate was timed
+            assert again == best and tdct.tdct_plan_info_get(pb)["tune"] == best
+            tdct.tdct_batch_run(pb)
+            B.check(tdct)
+        finally:
+            tdct.tdct_plan_free(pb)
+        info = tdct.tdct_tune_cache_info()
+        assert info["hits"] == 1 and info["stores"] == 0
+        C = Ragged(tdct, seed=22, big=True)  # more tiles: another size class
+        pc = tdct.tdct_batch_plan(C.descs, C.qtabs)
+        try:
+            tdct.tdct_autotune(pc, reps=1)
+            tdct.tdct_batch_run(pc)
+            C.check(tdct)
+        finally:
+            tdct.tdct_plan_free(pc)
+        info = tdct.tdct_tune_cache_info()
+        assert info["stores"] == 1 and info["entries"] == 2 and info["write_errors"] == 0
+    finally:
+        tdct.tdct_tune_cache_open(None)
+
+
 # ---- full-size workloads ------------------------------------------------------
 
 @pytest.mark.parametrize("tune", [None,

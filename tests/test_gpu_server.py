@@ -123,6 +123,54 @@ def test_mix_equals_alone_and_oracle(tdct):
         assert np.array_equal(mix[k], W.expected(k)), k
 
 
+def test_batches_take_tuned_shapes_from_the_cache(tdct, tmp_path):
+    """A server created with tune_cache = 1 launches its batches in the shapes
+    the autotune cache holds for their class: plans made of the same kind of
+    requests are tuned first (storing entries), then the requests arrive at
+    once; the cache is hit and every output equals one plain launch per
+    request, and sampled outputs equal the oracle."""
+    import torch
+    W = Workload(tdct, rate=10000.0, seconds=0.03, seed=57)
+    n = len(W.reqs)
+    try:
+        tdct.tdct_tune_cache_open(str(tmp_path / "tune.json"))
+        keep_alive = []
+        for lo, hi in ((0, 4), (0, 16), (16, 32)):
+            descs, qtabs = [], []
+            for k in range(lo, min(hi, n)):
+                m = W.meta[k]
+                qtabs.append(m["Q"])
+                if m["op"] == 0:
+                    out = torch.empty(m["w"] * m["h"] // 64 * 64, dtype=torch.int16, device="cuda")
+                    descs.append(tdct.image_desc(tdct.OP_ENCODE, m["w"], m["h"], qtab=len(qtabs) - 1,
+                                                 keep=m["keep"], src=W.dplanes[m["p"]], src_stride=POOL_SIDE,
+                                                 coef=out))
+                else:
+                    out = torch.empty(m["w"] * m["h"], dtype=torch.uint8, device="cuda")
+                    descs.append(tdct.image_desc(tdct.OP_DECODE, m["w"], m["h"], qtab=len(qtabs) - 1,
+                                                 coef=W.dcoefs[m["p"]], dst=out, dst_stride=m["w"]))
+                keep_alive.append(out)
+            plan = tdct.tdct_batch_plan(descs, qtabs)
+            try:
+                tdct.tdct_autotune(plan, reps=1)
+            finally:
+                tdct.tdct_plan_free(plan)
+        stored = tdct.tdct_tune_cache_info()
+        assert stored["entries"] >= 1
+        cfg = tdct.server_cfg(1 << 30, streams=2, max_batch=16, max_wait_us=0, batching=1, tune_cache=1)
+        mix, _, stats = _serve(tdct, W, cfg, idx=list(range(n)))
+        assert stats["failed"] == 0 and stats["mean_batch"] > 1.0
+        assert tdct.tdct_tune_cache_info()["hits"] > stored["hits"]
+    finally:
+        tdct.tdct_tune_cache_open(None)
+    per, _, _ = _serve(tdct, W, tdct.server_cfg(1 << 30, streams=4, max_batch=1, batching=0))
+    for k in range(n):
+        assert np.array_equal(mix[k], per[k]), k
+    rng = np.random.default_rng(3)
+    for k in sorted(rng.choice(n, 30, replace=False).tolist()):
+        assert np.array_equal(mix[k], W.expected(k)), k
+
+
 def test_tight_budget_queues_instead_of_failing(tdct):
     """A budget that holds only the largest output: requests wait in FIFO
     order for memory and all complete once earlier outputs are released."""
@@ -251,7 +299,7 @@ def test_resident_large_and_ragged_requests(tdct):
         nblk = (w // 8) * (h // 8)
         coefs = rng.integers(-2000, 2001, size=(nblk, 64)).astype(np.int16)
         cases.append((w, h, img, Q, coefs, torch.from_numpy(img).cuda(), torch.from_numpy(coefs).cuda()))
-    for workers in (3, 16):
+    for workers in (3, 16, 40):  # 2, 16 and 32 ticket queues, unevenly staffed at 3 and 40
         srv = tdct.tdct_server_create(tdct.server_cfg(1 << 30, resident=1, resident_workers=workers,
                                                       resident_idle_us=5000))
         try:
