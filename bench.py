@@ -694,9 +694,57 @@ def serving_cfg(tdct, mode, streams=4, resident_workers=0):
     # requests have ragged widths: batch launches take cached pixel accesses
     # (burst capacity +5-8 % measured; lone requests use the plain kernel
     # either way)
+    # batches take the autotune cache's shape for their class (tuned beforehand,
+    # tune_serving_classes), else cached pixel accesses
     return tdct.server_cfg(64 << 30, streams=streams, max_batch=64, max_wait_us=0,
                            batching=0 if mode == "per_request" else 1, max_batch_px=MAX_BATCH_PX,
-                           tune=dict(pixel_cache=1))
+                           tune=dict(pixel_cache=1), tune_cache=1)
+
+
+def tune_serving_classes(tdct, torch, P, rate=5000, seconds=4.0, sizes=(2, 4, 8, 16, 32, 64)):
+    """Fills the autotune cache with the classes serving batches fall in:
+    consecutive requests of the trace in groups of `sizes` requests (up to
+    MAX_BATCH_PX pixels, as the server cuts its batches) become batch plans,
+    and each is autotuned once. Servers created with tune_cache = 1 then
+    launch each batch in the shape stored for its class (or the nearest size
+    class). Returns the classes tuned."""
+    import synth
+    tr = synth.serving_trace(rate, seconds, seed=5)
+    n = len(tr["t"])
+    tuned, start = [], 0
+    stream = torch.cuda.current_stream()
+    for size in sizes:
+        descs, qtabs, outs, px = [], [], [], 0
+        k = start
+        while k < n and len(descs) < size:
+            w, h, s_, p = int(tr["w"][k]), int(tr["h"][k]), int(tr["s"][k]), k % SERVING_POOL
+            if descs and px + w * h > MAX_BATCH_PX:
+                break
+            qtabs.append(synth.qtable(1, s_))
+            if tr["op"][k] == 0:
+                out = torch.empty(w * h * 2, dtype=torch.uint8, device="cuda")
+                descs.append(tdct.image_desc(tdct.OP_ENCODE, w, h, qtab=len(qtabs) - 1, keep=64,
+                                             src=P["pool"][p], src_stride=SERVING_SIDE, coef=out))
+            else:
+                out = torch.empty(w * h, dtype=torch.uint8, device="cuda")
+                descs.append(tdct.image_desc(tdct.OP_DECODE, w, h, qtab=len(qtabs) - 1,
+                                             coef=P["coefs"][p], dst=out, dst_stride=w))
+            outs.append(out)
+            px += w * h
+            k += 1
+        start = k
+        if not descs:
+            break
+        plan = tdct.tdct_batch_plan(descs, qtabs)
+        try:
+            tune = tdct.tdct_autotune(plan, stream, reps=2)
+            info = tdct.tdct_plan_info_get(plan)
+        finally:
+            tdct.tdct_plan_free(plan)
+        tuned.append({"requests": len(descs), "mpx": round(px / 1e6, 1), "tiles": info["tiles"], "tune": tune})
+        del outs
+    torch.cuda.synchronize()
+    return tuned
 
 
 def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), streams=4,
@@ -714,6 +762,8 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
 
     import synth
     P = serving_pool(tdct, torch)
+    tuned = tune_serving_classes(tdct, torch, P)
+    log("serving: tuned batch classes %s" % json.dumps(tuned))
     hp = hc = ho = None
     if "host_io_batched" in modes:
         # pinned copies of the payloads and a few pinned output buffers of the
@@ -781,6 +831,7 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
         out[str(rate)] = res
     result = {"seconds_per_rate": {"batched": seconds, "per_request": seconds, "resident": aux_seconds,
                                    "host_io_batched": aux_seconds},
+              "batch_tune_classes": tuned,
               "streams": streams, "budget_gb": 64,
               "resident_workers": resident_workers or "four per CU", "rates": out}
     return result, {"P": P, "traces": traces, "seconds": seconds, "streams": streams}
@@ -793,10 +844,13 @@ def burst_leg(tdct, torch, modes, reps=3, seconds=4.0, rate=5000, resident_worke
     self-contained run for kernel traces and counters of the served forms."""
     import synth
     P = serving_pool(tdct, torch)
+    out = {}
+    if "batched" in modes:
+        out["batch_tune_classes"] = tune_serving_classes(tdct, torch, P)
     tr = synth.serving_trace(rate, seconds, seed=5)
     ra = serving_requests(tdct, tr, P)
     px = float((tr["w"] * tr["h"]).sum())
-    out = {"requests": len(ra), "gpx": round(px / 1e9, 2)}
+    out.update({"requests": len(ra), "gpx": round(px / 1e9, 2)})
     for mode in modes:
         runs = []
         for _ in range(reps):
@@ -1127,6 +1181,11 @@ def main():
                     help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--fused-tune", default="",
                     help="fixed launch shape 'WPG,GPC,TW[,XCD[,PC]]' for the fused round trip")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file (default: $TDCT_TUNE_CACHE, else "
+                         "~/.cache/tdct/autotune.json; '' turns it off): shapes tuned by an earlier "
+                         "run of the same kernel sources on this GPU architecture are taken without "
+                         "timing candidates again")
     ap.add_argument("--burst-only", default="",
                     help="only serve the 5000 req/s trace's requests arriving at once in these "
                          "comma-separated modes (batched, per_request, resident), for profiling")
@@ -1149,6 +1208,23 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
+    cache_path = args.tune_cache
+    if cache_path is None:
+        cache_path = os.environ.get("TDCT_TUNE_CACHE") or os.path.join(
+            os.path.expanduser("~"), ".cache", "tdct", "autotune.json")
+    if cache_path:
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+        except OSError:
+            pass  # the cache then counts write errors
+        try:
+            tdct.tdct_tune_cache_open(cache_path)
+        except tdct.TdctError as e:  # a file not in the cache's format: tune without it
+            log("autotune cache %s not used: %s" % (cache_path, e))
+            tdct.tdct_tune_cache_open(None)
+    else:
+        tdct.tdct_tune_cache_open(None)
+    cache_at_start = tdct.tdct_tune_cache_info()
 
     if args.burst_only:
         print(json.dumps({"burst": burst_leg(tdct, torch, args.burst_only.split(","), args.burst_reps,
@@ -1183,9 +1259,19 @@ def main():
     try:
         tune_e, tune_d = fixed
         if not args.no_tune and not args.tune:
+            hits0 = tdct.tdct_tune_cache_info()["hits"]
             tune_e = tdct.tdct_autotune(pe, stream, reps=3)
             tune_d = tdct.tdct_autotune(pd, stream, reps=3)
             log("autotune: encode %s decode %s" % (tune_e, tune_d))
+            if tdct.tdct_tune_cache_info()["hits"] > hits0:
+                # shapes from the cache: the candidates' ~0.5 s of launches,
+                # which also bring the clocks up, did not run; run as long
+                # untimed before the warm-up steps
+                t_end = time.perf_counter() + 0.5
+                while time.perf_counter() < t_end:
+                    tdct.tdct_batch_run(pe, stream)
+                    tdct.tdct_batch_run(pd, stream)
+                    torch.cuda.synchronize()
         wall, enc_ms, dec_ms = time_steps(tdct, torch, pe, pd, args.steps, args.warmup, stream)
     finally:
         tdct.tdct_plan_free(pe)
@@ -1298,6 +1384,11 @@ def main():
     if args.quality:
         log("quality leg...")
         result["quality"] = quality_leg(tdct, torch, stream)
+    info = tdct.tdct_tune_cache_info()
+    result["config"]["tune_cache"] = {"path": cache_path or None, "entries_at_start": cache_at_start["entries"],
+                                      "hits": info["hits"], "misses": info["misses"], "stores": info["stores"],
+                                      "write_errors": info["write_errors"], "batch_hits": info["batch_hits"],
+                                      "batch_misses": info["batch_misses"]}
     print(json.dumps(result), flush=True)
 
 

@@ -230,7 +230,8 @@ typedef struct {
     int32_t on;       /* 1 while a cache file is open */
     int32_t reserved;
     int64_t entries;  /* classes held */
-    int64_t hits, misses, stores, write_errors; /* since the cache was opened */
+    int64_t hits, misses, stores, write_errors; /* tdct_autotune, since the cache was opened */
+    int64_t batch_hits, batch_misses;          /* server batch launches (tune_cache = 1) */
 } tdct_tune_cache_stats;
 int tdct_tune_cache_open(const char* path);
 int tdct_tune_cache_info(tdct_tune_cache_stats* out);

@@ -83,7 +83,8 @@ class tdct_server_cfg(ctypes.Structure):
 class tdct_tune_cache_stats(ctypes.Structure):
     _fields_ = [("on", ctypes.c_int32), ("reserved", ctypes.c_int32), ("entries", ctypes.c_int64),
                 ("hits", ctypes.c_int64), ("misses", ctypes.c_int64), ("stores", ctypes.c_int64),
-                ("write_errors", ctypes.c_int64)]
+                ("write_errors", ctypes.c_int64), ("batch_hits", ctypes.c_int64),
+                ("batch_misses", ctypes.c_int64)]
 
 
 class tdct_request(ctypes.Structure):
@@ -314,7 +315,8 @@ def tdct_tune_cache_open(path):
 def tdct_tune_cache_info() -> dict:
     st = tdct_tune_cache_stats()
     _check(_lib.tdct_tune_cache_info(ctypes.byref(st)), "tdct_tune_cache_info")
-    return {k: getattr(st, k) for k in ("on", "entries", "hits", "misses", "stores", "write_errors")}
+    return {k: getattr(st, k) for k in ("on", "entries", "hits", "misses", "stores", "write_errors",
+                                        "batch_hits", "batch_misses")}
 
 
 def tdct_plan_info_get(plan) -> dict:

@@ -261,12 +261,12 @@ bool tune_cache_nearest(const std::string& arch, int ops, int64_t tiles, bool al
         if (k + d < 0) continue;
         auto it = c.entries.find(tune_key(arch, ops, (int64_t)1 << (k + d), aligned));
         if (it != c.entries.end()) {
-            c.stats.hits++;
+            c.stats.batch_hits++;
             *out = it->second;
             return true;
         }
     }
-    c.stats.misses++;
+    c.stats.batch_misses++;
     return false;
 }
 

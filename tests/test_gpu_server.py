@@ -160,7 +160,7 @@ def test_batches_take_tuned_shapes_from_the_cache(tdct, tmp_path):
         cfg = tdct.server_cfg(1 << 30, streams=2, max_batch=16, max_wait_us=0, batching=1, tune_cache=1)
         mix, _, stats = _serve(tdct, W, cfg, idx=list(range(n)))
         assert stats["failed"] == 0 and stats["mean_batch"] > 1.0
-        assert tdct.tdct_tune_cache_info()["hits"] > stored["hits"]
+        assert tdct.tdct_tune_cache_info()["batch_hits"] > 0
     finally:
         tdct.tdct_tune_cache_open(None)
     per, _, _ = _serve(tdct, W, tdct.server_cfg(1 << 30, streams=4, max_batch=1, batching=0))
