@@ -127,6 +127,14 @@ int tdct_stream_probe(int32_t kind, const void* src, void* dst, int64_t units, v
 
 const char* tdct_strerror(int status);
 const char* tdct_last_error(void);
+/* Diagnostics on stderr, one line per event, prefixed "[tdct <level>]":
+ * 1 errors (every failure tdct_last_error reports), 2 plans, autotune
+ * outcomes, the autotune cache and server lifecycle (create, resident
+ * launches, final statistics at destroy), 3 every server batch. The level
+ * starts at $TDCT_LOG (0, silent, when unset). Sets the level when
+ * level >= 0 (above 3 means 3) and returns the previous one; a negative
+ * argument only queries. */
+int tdct_log_level(int level);
 
 /* ---- batch form: many images of uneven sizes in one persistent launch -- */
 

@@ -148,6 +148,8 @@ _SIG = {
 for _name, _args in _SIG.items():
     getattr(_lib, _name).argtypes = _args
     getattr(_lib, _name).restype = ctypes.c_int
+_lib.tdct_log_level.argtypes = [ctypes.c_int]
+_lib.tdct_log_level.restype = ctypes.c_int
 _lib.tdct_strerror.argtypes = [ctypes.c_int]
 _lib.tdct_strerror.restype = ctypes.c_char_p
 _lib.tdct_last_error.restype = ctypes.c_char_p
@@ -305,6 +307,12 @@ def tdct_autotune(plan, stream=None, reps=3) -> dict:
     t = tdct_tune()
     _check(_lib.tdct_autotune(plan, _stream(stream), reps, ctypes.byref(t)), "tdct_autotune")
     return t.as_dict()
+
+
+def tdct_log_level(level=-1) -> int:
+    """Sets the library's diagnostic level on stderr (0 silent .. 3 every
+    server batch) when level >= 0; returns the previous level."""
+    return _lib.tdct_log_level(level)
 
 
 def tdct_tune_cache_open(path):

@@ -293,6 +293,10 @@ int tdct_batch_plan(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* q
             set_error("plan upload", e);
             return TDCT_EDEVICE;
         }
+        TDCT_LOG(2, "plan: %d images, %lld blocks, %zu tiles, ops 0x%x, %zu table bytes, shape %d/%d/%d/%d/%d",
+                 n, (long long)(p->blk_off.empty() ? 0 : p->blk_off.back()), p->tiles.size(), p->ops,
+                 p->dev_bytes, p->tune.waves_per_group, p->tune.groups_per_cu, p->tune.tile_waves,
+                 p->tune.xcd_remap, p->tune.pixel_cache);
         *out = p.release();
         return TDCT_OK;
     });
@@ -364,6 +368,8 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
             free_graph(p);  // a captured graph holds the launch shape it was made with
             p->tune = cached;
             if (best) *best = cached;
+            TDCT_LOG(2, "autotune: %s: cached shape %d/%d/%d/%d/%d", key.c_str(), cached.waves_per_group,
+                     cached.groups_per_cu, cached.tile_waves, cached.xcd_remap, cached.pixel_cache);
             return TDCT_OK;
         }
         hipStream_t s = (hipStream_t)stream;
@@ -401,6 +407,7 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
         std::vector<std::vector<float>> finals;
         size_t k = 0;
         tdct_tune winner = saved;
+        float winner_ms = 0;
         int st = TDCT_OK;
         int rounds = 0;
         // Stage 1: every launch shape (persistent grids of 1..16 resident waves
@@ -459,6 +466,7 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
             for (size_t c = 1; c < k; ++c)
                 if (median(finals[c]) < median(finals[b])) b = c;
             winner = cands[b].t;
+            winner_ms = median(finals[b]);
         }
     done:
         (void)hipEventDestroy(e0);
@@ -470,6 +478,9 @@ int tdct_autotune(tdct_plan* p, void* stream, int32_t reps, tdct_tune* best) {
         free_graph(p);  // a captured graph holds the launch shape it was made with
         p->tune = winner;
         if (best) *best = winner;
+        TDCT_LOG(2, "autotune: %s: %zu shapes timed, kept %d/%d/%d/%d/%d (median %.4f ms over %d rounds)",
+                 key.c_str(), cands.size(), winner.waves_per_group, winner.groups_per_cu, winner.tile_waves,
+                 winner.xcd_remap, winner.pixel_cache, (double)winner_ms, rounds);
         tune_cache_put(key, winner);
         return TDCT_OK;
     });

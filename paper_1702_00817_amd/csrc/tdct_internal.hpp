@@ -16,6 +16,17 @@ namespace tdct {
 void set_error(const char* what, hipError_t e);
 void set_error_text(const char* what);
 
+// Diagnostics on stderr, one line each, by level: 1 errors (everything
+// set_error records), 2 plans, autotuning, the autotune cache and server
+// lifecycle, 3 every server batch. The level comes from $TDCT_LOG (0 when
+// unset) or tdct_log_level.
+int log_level();
+void log_line(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+#define TDCT_LOG(level, ...)                                                       \
+    do {                                                                           \
+        if (::tdct::log_level() >= (level)) ::tdct::log_line((level), __VA_ARGS__); \
+    } while (0)
+
 // Runs the body of a C-ABI call: a host allocation failure (or any other C++
 // exception) becomes a status code, so no exception crosses the ABI.
 template <class F>

@@ -301,6 +301,13 @@ int stage_input(const BatchItem& it, hipStream_t st) {
 
 // Builds tables for the batch and launches it on the slot. No lock held.
 int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>& items) {
+    if (log_level() >= 3) {
+        int64_t px = 0;
+        for (const BatchItem& it : items) px += (int64_t)it.r.w * it.r.h;
+        log_line(3, "server batch: %zu requests, %lld px, slot %d, %s", items.size(), (long long)px,
+                 (int)(&sl - s->slots.data()),
+                 s->fake ? "fake device" : (!s->cfg.batching || items.size() == 1 ? "plain launches" : "batch kernel"));
+    }
     if (s->fake) {
         if (!sl.fake_launch_fail) return TDCT_OK;
         set_error_text("fake device: launch failed after its work was queued");
@@ -390,9 +397,12 @@ int launch_batch_on_slot(tdct_server* s, Slot& sl, const std::vector<BatchItem>&
         // the autotune cache's shape for this batch's class, if asked for
         // and stored
         tdct_tune tune = s->cfg.tune;
-        if (s->cfg.tune_cache)
-            (void)tune_cache_nearest(s->arch, ops, (int64_t)tiles.size(),
-                                     pixels_aligned(imgs.data(), imgs.size()), &tune);
+        const bool cached = s->cfg.tune_cache &&
+                            tune_cache_nearest(s->arch, ops, (int64_t)tiles.size(),
+                                               pixels_aligned(imgs.data(), imgs.size()), &tune);
+        TDCT_LOG(3, "server batch kernel: %zu tiles, ops 0x%x, shape %d/%d/%d/%d/%d%s", tiles.size(), ops,
+                 tune.waves_per_group, tune.groups_per_cu, tune.tile_waves, tune.xcd_remap, tune.pixel_cache,
+                 cached ? " (autotune cache)" : "");
         st = launch_batch((const Tile*)dbase, (const ImgDesc*)(dbase + tb),
                           (const QConst*)(dbase + tb + ib), (uint32_t)tiles.size(), ops, tune,
                           s->num_cus, sl.stream);
@@ -733,6 +743,7 @@ void resident_free(tdct_server* s) {
 int resident_enqueue(tdct_server* s) {
     Resident& R = s->res;
     R.epoch++;
+    TDCT_LOG(2, "resident kernel launch %u (%d worker waves)", R.epoch, R.workers);
     s->batches++;
     R.args.epoch = R.epoch;
     // Tickets the last launch's workers left with are beyond its last
@@ -925,6 +936,9 @@ void scheduler(tdct_server* s) {
             if (fired) {
                 s->last_activity_us = now;
                 const int bs = (int)sl.tickets.size();
+                if (status != TDCT_OK)
+                    TDCT_LOG(1, "error: a batch of %d requests failed on the device%s", bs,
+                             s->fake ? " (fake device: injected)" : "");
                 for (uint64_t t : sl.tickets) finish_request(s, t, status, bs, now);
                 sl.tickets.clear();
                 sl.busy = false;
@@ -1038,6 +1052,14 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
             if (st) return st;
         }
         s->worker = std::thread(scheduler, s.get());
+        if (s->cfg.resident)
+            TDCT_LOG(2, "server create: resident, %lld byte arena, %d worker waves, %u ticket queues, %u queue slots%s",
+                     (long long)cfg->budget_bytes, s->res.workers, s->res.args.nq, s->res.ring_jobs,
+                     s->fake ? ", fake device" : "");
+        else
+            TDCT_LOG(2, "server create: %s, %lld byte arena, %d streams, batches of at most %d requests / %lld px%s",
+                     s->cfg.batching ? "continuous batching" : "one launch per request", (long long)cfg->budget_bytes,
+                     s->cfg.streams, s->cfg.max_batch, (long long)s->cfg.max_batch_px, s->fake ? ", fake device" : "");
         *out = s.release();
         return TDCT_OK;
     });
@@ -1202,6 +1224,14 @@ void tdct_server_destroy(tdct_server* s) {
     }
     s->wake.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    if (log_level() >= 2) {
+        tdct_stats st;
+        if (tdct_server_stats(s, &st) == TDCT_OK)
+            log_line(2, "server destroy: %lld submitted, %lld completed, %lld failed, %lld rejected, %lld launches, "
+                        "mean batch %.2f, p50 %.1f us, p99 %.1f us, arena high water %lld bytes",
+                     (long long)st.submitted, (long long)st.completed, (long long)st.failed, (long long)st.rejected,
+                     (long long)st.batches, st.mean_batch, st.p50_us, st.p99_us, (long long)st.arena_high_water);
+    }
     if (s->cfg.resident) resident_free(s);
     if (s->fake) {
         free(s->arena_base);

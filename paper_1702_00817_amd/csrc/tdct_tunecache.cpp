@@ -154,6 +154,7 @@ int load_locked(TuneCache& c, const char* path) {
     c.path = path;
     c.on = true;
     c.stats.entries = (int64_t)c.entries.size();
+    TDCT_LOG(2, "autotune cache: %s, %zu entries", path, c.entries.size());
     return TDCT_OK;
 }
 
@@ -187,6 +188,7 @@ void write_locked(TuneCache& c) {
     if (!ok) {
         (void)remove(tmp.c_str());
         c.stats.write_errors++;
+        TDCT_LOG(1, "autotune cache: could not write %s", c.path.c_str());
     }
 }
 

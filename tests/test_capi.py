@@ -480,3 +480,44 @@ def test_fake_resident_replay_and_shutdown_with_work_in_flight(tdct):
             tdct.tdct_server_submit(s, _req(tdct, 0, 64, 64))
     finally:
         tdct.tdct_server_destroy(s)  # the ten in flight finish first
+
+
+# ---- diagnostics -------------------------------------------------------------
+
+_LOG_SCRIPT = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import paper_1702_00817_amd as tdct
+s = tdct.tdct_server_create(tdct.server_cfg(1 << 22, streams=1, max_batch=1, fake_device_us=200,
+                                            fake_fail_every=3))
+for k in range(6):
+    tdct.tdct_server_submit(s, tdct.request(k % 2, 64, 32, 0x1000, np.ones(64)))
+tdct.tdct_server_drain(s)
+tdct.tdct_server_destroy(s)
+print("level", tdct.tdct_log_level())
+"""
+
+
+@pytest.mark.parametrize("level", ["", "1", "2", "3"])
+def test_log_levels_on_stderr(level):
+    """TDCT_LOG sets the stderr diagnostics: nothing by default, errors at 1,
+    server lifecycle at 2, every batch at 3 (fake device, injected failures)."""
+    import subprocess
+    import sys
+    env = dict(os.environ)
+    env.pop("TDCT_LOG", None)
+    if level:
+        env["TDCT_LOG"] = level
+    r = subprocess.run([sys.executable, "-c", _LOG_SCRIPT, ROOT], env=env, stdin=subprocess.DEVNULL,
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().endswith("level %d" % (int(level) if level else 0))
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[tdct ")]
+    n = int(level) if level else 0
+    assert all(int(l[6]) <= n for l in lines)  # nothing above the level
+    has = lambda what: any(what in l for l in lines)
+    assert has("error: a batch of 1 requests failed on the device (fake device") == (n >= 1)
+    assert has("server create: continuous batching") == (n >= 2)
+    assert has("server destroy: 6 submitted") == (n >= 2)
+    assert has("server batch: ") == (n >= 3)
