@@ -19,7 +19,7 @@ HOSTCHECK_SRC = os.path.join(ROOT, "tests", "hostcheck.cpp")
 HOSTCHECK_LIB = os.path.join(ROOT, "tests", "libhostcheck.so")
 
 SOURCES = ["tdct_kernels.hip", "tdct_probe.hip", "tdct_resident.hip", "tdct_static.hip",
-           "tdct_batch.cpp", "tdct_server.cpp", "tdct_tunecache.cpp"]
+           "tdct_batch.cpp", "tdct_server.cpp", "tdct_tunecache.cpp", "tdct_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
