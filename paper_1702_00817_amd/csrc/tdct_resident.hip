@@ -168,13 +168,13 @@ __device__ __forceinline__ void code_item(const ImgDesc& d, const QConst& qc, ui
         }
     } else {
         DecChunks C;
-        dec_load(d, first, count, lane, C);
+        dec_load<PX_COHERENT>(d, first, count, lane, C);
         for (uint32_t tile = tile0; tile < tile1; ++tile) {
             const bool more = tile + 1 < tile1;
             const uint32_t nfirst = first + tb;
             const uint32_t ncount = more ? min(tb, nblk - nfirst) : 0u;
             dec_tile<PX_COHERENT>(d, qc, first, count, lane, wl, C, [&]() {
-                if (more) dec_load(d, nfirst, ncount, lane, C);
+                if (more) dec_load<PX_COHERENT>(d, nfirst, ncount, lane, C);
             });
             first = nfirst;
             count = ncount;
@@ -276,14 +276,16 @@ __device__ void worker_wave(const ResidentArgs& a, uint32_t worker, uint32_t lan
         if (t < cur_base || t >= cur_end) {
             // A new job: item t's entry, the job copy and count were released
             // before the publication that covered t, and the job's inputs
-            // were written before it was queued; the acquire also drops any
-            // older copy of them from this wave's caches.
+            // were written before it was queued. All of them are read with
+            // coherent loads (the entry and the job copy here, the inputs in
+            // the tile code), which see memory as it is now even where this
+            // XCD's L2 holds an older copy, so no acquire (an invalidate of
+            // the whole L2) is needed per job.
             count_off();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             slot = __builtin_amdgcn_readfirstlane(__hip_atomic_load(&a.item_slot[(uint32_t)t & imask],
                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
                    (a.ring_jobs - 1);
-            jl[k] = reinterpret_cast<const v4u*>(a.jobs + slot)[k];
+            jl[k] = ld_wt4(a.jobs + slot, 16u * k, (uint32_t)sizeof(ResidentJob));
             lds_fence();
             // the job's pointers came through LDS
             d = global_desc(uniform_copy(&J->d));

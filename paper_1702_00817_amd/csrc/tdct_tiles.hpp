@@ -63,6 +63,25 @@ __device__ __forceinline__ void st_wt2(void* p, v2u v) {
 __device__ __forceinline__ void st_wt1(uint8_t* p, uint8_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Loads that never return a stale L2 line (sc1): what another agent (a copy
+// engine, a kernel on another XCD) wrote to memory before the load is seen.
+// A kernel that keeps running while its inputs change between requests reads
+// them this way instead of invalidating its XCD's whole L2.
+__device__ __forceinline__ v2u ld_wt2(const void* p) {
+    return __builtin_bit_cast(v2u, __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ uint32_t ld_wt1(const uint8_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// 16-byte load at base + off (base wave-uniform, off per lane, in bytes);
+// lanes with off >= limit read zero.
+__device__ __forceinline__ v4u ld_wt4(const void* base, uint32_t off, uint32_t limit) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)limit, (int)kBufRsrcWord3);
+    return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, kBufSc1Nt));
+}
+
 // 16-byte store at base + off (base wave-uniform, off per lane, both in
 // bytes); lanes with off >= limit store nothing.
 __device__ __forceinline__ void st_wt4(void* base, uint32_t off, uint32_t limit, v4u v) {
@@ -72,9 +91,10 @@ __device__ __forceinline__ void st_wt4(void* base, uint32_t off, uint32_t limit,
 
 // Pixel-plane (and output) access policy, a compile-time parameter of the
 // tile code. PX_STREAM and PX_CACHED are the batch kernels' pixel cache
-// policies (below). PX_COHERENT streams loads and writes every output --
-// pixels and coefficients -- through L2 (st_wt*), for kernels whose waves
-// report finished outputs while the kernel keeps running.
+// policies (below). PX_COHERENT reads every input with coherent loads
+// (ld_wt*) and writes every output -- pixels and coefficients -- through L2
+// (st_wt*), for kernels whose waves report finished outputs, and take new
+// inputs, while the kernel keeps running.
 enum { PX_STREAM = 0, PX_CACHED = 1, PX_COHERENT = 2 };
 
 // Pixel-plane accesses under the cache policy a launch picks. Streaming
@@ -88,6 +108,8 @@ template <int PC>
 __device__ __forceinline__ v2u ld_px(const void* p) {
     if constexpr (PC == PX_CACHED)
         return *reinterpret_cast<const v2u*>(p);
+    else if constexpr (PC == PX_COHERENT)
+        return ld_wt2(p);
     else
         return ld_nt2(p);
 }
@@ -188,9 +210,13 @@ __device__ __forceinline__ void stage_out(v4u* wl, const v4u (&mine)[CPL], uint3
 
 // Loads the run of 512 chunks at src (only its first nchunks; the rest read
 // as zero): chunk 64 k + lane into tmp[k].
+template <int PC = PX_STREAM>
 __device__ __forceinline__ void stage_load(const v4u* src, uint32_t nchunks, uint32_t lane,
                                            v4u (&tmp)[8]) {
-    if (nchunks == 512) {
+    if constexpr (PC == PX_COHERENT) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tmp[k] = ld_wt4(src, 16u * (64u * k + lane), 16u * nchunks);
+    } else if (nchunks == 512) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) tmp[k] = ld_nt4(src + 64u * k + lane);
     } else {
@@ -233,10 +259,15 @@ __device__ __forceinline__ void load_rows8(const uint8_t* p, int64_t stride, int
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const uint8_t* q = p + r * stride;
-            R[r][0] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) |
-                      ((uint32_t)q[3] << 24);
-            R[r][1] = (uint32_t)q[4] | ((uint32_t)q[5] << 8) | ((uint32_t)q[6] << 16) |
-                      ((uint32_t)q[7] << 24);
+            if constexpr (PC == PX_COHERENT) {
+                R[r][0] = ld_wt1(q) | (ld_wt1(q + 1) << 8) | (ld_wt1(q + 2) << 16) | (ld_wt1(q + 3) << 24);
+                R[r][1] = ld_wt1(q + 4) | (ld_wt1(q + 5) << 8) | (ld_wt1(q + 6) << 16) | (ld_wt1(q + 7) << 24);
+            } else {
+                R[r][0] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) |
+                          ((uint32_t)q[3] << 24);
+                R[r][1] = (uint32_t)q[4] | ((uint32_t)q[5] << 8) | ((uint32_t)q[6] << 16) |
+                          ((uint32_t)q[7] << 24);
+            }
         }
     }
 }
@@ -552,9 +583,10 @@ struct DecChunks {
     v4u c[8];
 };
 
+template <int PC = PX_STREAM>
 __device__ __forceinline__ void dec_load(const ImgDesc& d, uint32_t first, uint32_t count,
                                          uint32_t lane, DecChunks& C) {
-    stage_load(reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, C.c);
+    stage_load<PC>(reinterpret_cast<const v4u*>(d.coef) + (int64_t)first * 8, 8 * count, lane, C.c);
 }
 
 // Decodes lane's block from its 8 chunks and stores its pixels.

@@ -250,6 +250,50 @@ def test_resident_mix_equals_stream_mode_and_oracle(tdct):
         assert np.array_equal(res[k], W.expected(k)), k
 
 
+def test_resident_sees_inputs_rewritten_between_requests(tdct):
+    """The resident kernel reads each request's inputs as they are when the
+    request is submitted, also where an earlier request read the same buffer
+    (so its XCD's L2 may hold the old bytes) and the kernel has kept running
+    since. One buffer of pixels and one of coefficients are rewritten before
+    every request; every output must equal the oracle on the new content."""
+    import torch
+    hip = _hip()
+    side = 1024
+    rng = np.random.default_rng(77)
+    X = torch.empty((side, side), dtype=torch.uint8, device="cuda")
+    C = torch.empty(((side // 8) ** 2, 64), dtype=torch.int16, device="cuda")
+    srv = tdct.tdct_server_create(tdct.server_cfg(1 << 30, resident=1, resident_idle_us=500000))
+    got, cases = [], []
+    try:
+        inputs = [(synth.textured(side, side, 9000 + k),
+                   rng.integers(-400, 401, size=((side // 8) ** 2, 64)).astype(np.int16)) for k in range(24)]
+        for k, (img, coefs) in enumerate(inputs):
+            X.copy_(torch.from_numpy(img))
+            C.copy_(torch.from_numpy(coefs))
+            # the copies' own stream only: a device-wide synchronize would wait
+            # for the resident kernel to go idle and exit
+            torch.cuda.current_stream().synchronize()
+            w, h = [(1024, 1024), (512, 1024), (1024, 256), (776, 520)][k % 4]
+            Q = synth.qtable(1, 1 + k % 8)
+            te = tdct.tdct_server_submit(srv, tdct.request(tdct.OP_ENCODE, w, h, X, Q, in_stride=side))
+            td = tdct.tdct_server_submit(srv, tdct.request(tdct.OP_DECODE, w, h, C, Q))
+            re, rd = tdct.tdct_server_wait(srv, te), tdct.tdct_server_wait(srv, td)
+            assert re.status == tdct.TDCT_OK and rd.status == tdct.TDCT_OK
+            got.append((_read(hip, re.output, re.output_bytes), _read(hip, rd.output, rd.output_bytes)))
+            cases.append((w, h, Q))
+            tdct.tdct_server_release(srv, te)
+            tdct.tdct_server_release(srv, td)
+        # the kernel stayed up across requests (it lives one second at a time)
+        assert tdct.tdct_server_stats(srv)["batches"] <= 2
+    finally:
+        tdct.tdct_server_destroy(srv)
+    for k, ((img, coefs), (w, h, Q), (ge, gd)) in enumerate(zip(inputs, cases, got)):
+        want_e = O.quantise(np.ascontiguousarray(img[:h, :w]), Q, 64).view(np.uint8).reshape(-1)
+        want_d = O.inverse(coefs[:(w // 8) * (h // 8)], Q, w, h).reshape(-1)
+        assert np.array_equal(ge, want_e), (k, "encode")
+        assert np.array_equal(gd, want_d), (k, "decode")
+
+
 def test_resident_single_worker_and_wrap(tdct):
     """One worker wave claims every tile; 4 queue slots and 256 tile slots."""
     W = Workload(tdct, rate=20000.0, seconds=0.005, seed=59)
