@@ -748,13 +748,16 @@ def tune_serving_classes(tdct, torch, P, rate=5000, seconds=4.0, sizes=(2, 4, 8,
 
 
 def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), streams=4,
-                resident_workers=0, modes=("batched", "per_request", "resident", "host_io_batched")):
+                resident_workers=0, modes=("resident", "per_request", "batched", "host_io_batched"),
+                batched_seconds=None):
     """Poisson encode/decode requests (the serving workload: sides log-uniform
     multiples of 8 in [32, 8192], aspect <= 4, s in {1..8}) served by
     continuous batching and by one plain launch per request for `seconds`
-    per rate, with device-resident payloads; by the resident polling kernel
-    and with host payloads copied over PCIe (host_io_batched, the
-    PCIe-inclusive rate) for `aux_seconds` per rate. Per mode: latency
+    per rate, with device-resident payloads: the resident polling kernel
+    (the served form) and one plain launch per request for `seconds`,
+    continuous batching into launched batch kernels for `batched_seconds`,
+    and batching with host payloads copied over PCIe (host_io_batched, the
+    PCIe-inclusive rate) for `aux_seconds`. Per mode: latency
     percentiles, the tail's make-up (share of p99-and-above requests served in
     a batch of more than one, their mean size) and small-request percentiles.
     Returns (result, context for the oracle check)."""
@@ -776,7 +779,8 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
     for rate in rates:
         res = {}
         for mode in modes:
-            secs = seconds if mode in ("batched", "per_request") else aux_seconds
+            secs = {"resident": seconds, "per_request": seconds,
+                    "batched": batched_seconds or seconds}.get(mode, aux_seconds)
             tr = synth.serving_trace(rate, secs, seed=5)
             traces[(rate, secs)] = tr
             px = (tr["w"] * tr["h"]).astype(np.int64)
@@ -829,8 +833,19 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
                                         "mean_batch": round(stats["mean_batch"], 2),
                                         "failed": int(sum(1 for s_ in st if s_ != 0))}
         out[str(rate)] = res
-    result = {"seconds_per_rate": {"batched": seconds, "per_request": seconds, "resident": aux_seconds,
-                                   "host_io_batched": aux_seconds},
+    # the served form against one launch per request, per rate
+    summary = {"served_form": "resident", "compared_with": "per_request", "rates": {}}
+    for rate in rates:
+        r = out[str(rate)]
+        if "resident" in r and "per_request" in r:
+            a, b = r["resident"], r["per_request"]
+            summary["rates"][str(rate)] = {k: a[k] for k in ("p50_us", "p99_us", "p999_us")}
+            summary["rates"][str(rate)].update({"per_request_" + k: b[k] for k in ("p50_us", "p99_us", "p999_us")})
+    burst = out[str(max(rates))]
+    summary["burst_gpx_s"] = {m: burst["burst_" + m]["gpx_s"] for m in modes if "burst_" + m in burst}
+    result = {"summary": summary,
+              "seconds_per_rate": {"resident": seconds, "per_request": seconds,
+                                   "batched": batched_seconds or seconds, "host_io_batched": aux_seconds},
               "batch_tune_classes": tuned,
               "streams": streams, "budget_gb": 64,
               "resident_workers": resident_workers or "four per CU", "rates": out}
@@ -895,7 +910,8 @@ def cpu_baseline_serving(tdct, torch, ctx, rates, frac=0.01, big_px=32 << 20, di
     """The served outputs against the oracle, outside the timed replays: for
     every rate, a seeded `frac` of the trace plus every request of at least
     32 Mpx is served again (same configuration, all at once, outputs kept),
-    in the batched and in the per-request mode, and each output is compared
+    by the resident kernel, by batched launches and by one launch per
+    request, and each output is compared
     in full with the oracle's.
 
     The oracle encodes every payload plane under every table the trace uses
@@ -956,7 +972,7 @@ def cpu_baseline_serving(tdct, torch, ctx, rates, frac=0.01, big_px=32 << 20, di
         outb = np.where(tr["op"] == 0, 2 * px, px)
         res = {"requests": int(len(sample)), "random": int(len(rand)), "at_least_32mpx": int(len(big)),
                "gpx": round(float(px[sample].sum()) / 1e9, 2)}
-        for mode in ("batched", "per_request"):
+        for mode in ("resident", "batched", "per_request"):
             bad = 0
             srv = tdct.tdct_server_create(serving_cfg(tdct, mode, ctx["streams"]))
             try:
@@ -1006,7 +1022,7 @@ def cpu_baseline_serving(tdct, torch, ctx, rates, frac=0.01, big_px=32 << 20, di
                               "mismatches_vs_planes": int(direct_bad)},
             "oracle_planes": {"gpx_s": round(planes_px / t_planes / 1e9, 4), "seconds": round(t_planes, 2)},
             "sample": "seeded %.0f %% of each %g-s trace plus every request of >= 32 Mpx, served again "
-                      "(batched and per-request modes) and compared in full with windows of the oracle's "
+                      "(resident, batched and per-request modes) and compared in full with windows of the oracle's "
                       "whole-plane encodings and block-wise decodings (%d threads)"
                       % (100 * frac, ctx["seconds"], threads)}
 
@@ -1172,9 +1188,11 @@ def main():
                          "'WPG,GPC,TW[,XCD[,PC]]:WPG,GPC,TW[,XCD[,PC]]' for the encoder and the "
                          "decoder (PC: cached pixel accesses)")
     ap.add_argument("--serving-seconds", type=float, default=60.0,
-                    help="trace length per rate for the batched and per-request serving modes")
+                    help="trace length per rate for the resident (served form) and per-request modes")
+    ap.add_argument("--serving-batched-seconds", type=float, default=20.0,
+                    help="trace length per rate for continuous batching into launched kernels")
     ap.add_argument("--serving-aux-seconds", type=float, default=4.0,
-                    help="trace length per rate for the resident and host-payload modes and the burst")
+                    help="trace length per rate for host payloads and the burst")
     ap.add_argument("--quality", action="store_true",
                     help="also run the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--legs", default="",
@@ -1377,7 +1395,8 @@ def main():
         del bctx
     if want("serving"):
         log("serving leg...")
-        result["serving"], sctx = serving_leg(tdct, torch, args.serving_seconds, args.serving_aux_seconds)
+        result["serving"], sctx = serving_leg(tdct, torch, args.serving_seconds, args.serving_aux_seconds,
+                                              batched_seconds=args.serving_batched_seconds)
         cpu("serving", cpu_baseline_serving, tdct, torch, sctx, (200, 1000, 5000))
         del sctx
         torch.cuda.empty_cache()
