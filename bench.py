@@ -231,15 +231,7 @@ def latency_leg(tdct, torch, stream, side=512, reps=100):
         "roundtrip_keep10": lambda: tdct.tdct_roundtrip(src, side, side, side, one, 10, None, rt, side,
                                                         stream),
     }
-    # Spin-kernel cycles for about 20 ms, from one timed spin.
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        torch.cuda._sleep(1 << 20)
-        a.record(stream)
-        torch.cuda._sleep(1 << 22)
-        b.record(stream)
-    torch.cuda.synchronize()
-    hold = int((1 << 22) * 20.0 / max(a.elapsed_time(b), 1e-3))
+    hold = spin_cycles(torch, stream, 20.0)
     out = {"side": side, "reps": reps}
     for name, f in ops.items():
         f()
@@ -1135,38 +1127,84 @@ def cpu_baseline_video(ctx, min_s=3.0):
                             "sample": "first %d planes in %.1f s" % (done1, dt1)}}
 
 
-def plain_leg(tdct, torch, stream, sides=(4096, 8192, 16384), reps=10):
+def spin_cycles(torch, stream, ms):
+    """Cycles of torch's spin kernel that hold `stream` for about `ms`
+    milliseconds, from one timed spin."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(1 << 20)
+        a.record(stream)
+        torch.cuda._sleep(1 << 22)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return int((1 << 22) * ms / max(a.elapsed_time(b), 1e-3))
+
+
+def queued_run_ms(torch, stream, f, n, hold):
+    """Device time of `n` back-to-back calls of f: queued behind a spin
+    kernel, with one event before the first and one after the last, so that
+    neither the host's launch time nor per-call event markers enter. Returns
+    None if the spin ended before the last call was queued (the run then saw
+    an idle queue)."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(hold)
+    a.record(stream)
+    for _ in range(n):
+        f()
+    b.record(stream)
+    in_time = not a.query()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) if in_time else None
+
+
+def plain_leg(tdct, torch, stream, sides=(4096, 8192, 16384), rounds=5, reps=10):
     """One image per call through the plain C-ABI calls: tdct_quantise
     (encode, keep 64) and tdct_inverse (decode) on one blob-field image of
-    4096^2, 8192^2 and 16384^2, Q = 1 + 3(i + j). Each is the median of `reps`
-    event-timed calls queued back to back behind a spin kernel (so the events
-    see device time only); 3 B/px algorithmic against 8 TB/s."""
+    4096^2, 8192^2 and 16384^2, Q = 1 + 3(i + j); 3 B/px algorithmic against
+    8 TB/s. `ms` is the device time per call of a run of back-to-back calls
+    (about 1.6 Gpx per run, at least 10 calls) timed with one event pair,
+    median of `rounds` runs: the rate of a stream of plain calls. Beside it,
+    `ms_event_per_call` is the median of `reps` calls each bracketed by its
+    own events, which adds the event markers' overhead (a few microseconds)
+    to every call. Both queue the calls behind a spin kernel, so they see
+    device time only."""
     import synth
     Q = tdct.qtable(synth.qtable(1, 3))
+    hold = spin_cycles(torch, stream, 20.0)
     out = {}
     for side in sides:
         src = torch.from_numpy(synth.plane(side, side, 4242)).cuda()
         q = torch.empty(((side // 8) ** 2, 64), dtype=torch.int16, device="cuda")
         dst = torch.empty_like(src)
         px = side * side
+        n = max(10, min(100, int(1.6e9 / px)))
         calls = {"encode": lambda: tdct.tdct_quantise(src, side, side, side, Q, 64, q, stream),
                  "decode": lambda: tdct.tdct_inverse(q, Q, side, side, dst, side, stream)}
         r = {}
         for name, f in calls.items():
             f()
             torch.cuda.synchronize()
+            runs = []
+            for _ in range(rounds):
+                t = queued_run_ms(torch, stream, f, n, hold)
+                if t is None:
+                    raise RuntimeError("plain leg: the spin kernel ended before %d calls were queued" % n)
+                runs.append(t / n)
+            ms = sorted(runs)[rounds // 2]
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
             with torch.cuda.stream(stream):
-                torch.cuda._sleep(1 << 21)
+                torch.cuda._sleep(hold)
             ev[0].record(stream)
             for k in range(reps):
                 f()
                 ev[k + 1].record(stream)
             torch.cuda.synchronize()
-            ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))[reps // 2]
+            per_call = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))[reps // 2]
             gbs = 3 * px / (ms / 1e3) / 1e9
-            r[name] = {"ms": round(ms, 4), "gpx_s": round(px / (ms / 1e3) / 1e9, 1), "gbs": round(gbs, 1),
-                       "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+            r[name] = {"ms": round(ms, 4), "calls_per_run": n, "gpx_s": round(px / (ms / 1e3) / 1e9, 1),
+                       "gbs": round(gbs, 1), "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4),
+                       "ms_event_per_call": round(per_call, 4)}
         out[str(side)] = r
         del src, q, dst
         torch.cuda.empty_cache()
