@@ -228,7 +228,8 @@ int tdct_autotune(tdct_plan* plan, void* stream, int32_t reps, tdct_tune* best);
  * address, width and stride are multiples of 128 bytes -- and on a hit applies
  * the stored shape without timing anything; on a miss it times candidates as
  * below and stores the winner, rewriting the file (through a temporary file
- * and a rename). Servers created with tune_cache = 1 launch each batch in the
+ * and a rename; entries other processes stored in the file meanwhile are
+ * kept, this process's winning on the same class). Servers created with tune_cache = 1 launch each batch in the
  * shape stored for its class, or for the nearest size class within a factor
  * of 4 (tdct_server_cfg). The file holds one object:
  * {"format": "tdct-autotune-1", "entries": {"gfx950/src=<hash>/ops=1/tiles=17/aligned=1":

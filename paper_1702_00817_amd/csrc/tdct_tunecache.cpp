@@ -17,8 +17,9 @@
 //       "<key>": [waves_per_group, groups_per_cu, tile_waves, xcd_remap, pixel_cache],
 //       ... } }
 //
-// It is read once when the cache is opened and rewritten whole (through a
-// temporary file and a rename) after each new entry.
+// It is read when the cache is opened and rewritten whole (through a
+// temporary file and a rename) after each new entry, keeping the entries
+// other processes stored in it meanwhile.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -128,6 +129,19 @@ int parse(const std::string& text, std::map<std::string, tdct_tune>& out) {
     return s.p == s.end ? TDCT_OK : TDCT_EINVAL;
 }
 
+// Reads the whole file at `path`: 1 if read, 0 if it cannot be opened, -1
+// on a read error.
+int read_file(const char* path, std::string* text) {
+    FILE* f = fopen(path, "rb");
+    if (!f) return 0;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) text->append(buf, n);
+    const bool bad = ferror(f) != 0;
+    fclose(f);
+    return bad ? -1 : 1;
+}
+
 // Loads `path` into the cache and turns it on (a missing file is an empty
 // cache). Caller holds the lock.
 int load_locked(TuneCache& c, const char* path) {
@@ -136,15 +150,10 @@ int load_locked(TuneCache& c, const char* path) {
     c.path.clear();
     if (!path || !*path) return TDCT_OK;
     std::map<std::string, tdct_tune> e;
-    FILE* f = fopen(path, "rb");
-    if (f) {
-        std::string text;
-        char buf[4096];
-        size_t n;
-        while ((n = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
-        const bool bad = ferror(f) != 0;
-        fclose(f);
-        if (bad) return TDCT_EINVAL;
+    std::string text;
+    const int got = read_file(path, &text);
+    if (got < 0) return TDCT_EINVAL;
+    if (got > 0) {
         if (parse(text, e)) {
             set_error_text("autotune cache: file is not in the cache's format");
             return TDCT_EINVAL;
@@ -166,8 +175,15 @@ void ensure_env_locked(TuneCache& c) {
 }
 
 // Writes the whole cache through a temporary file and a rename, so a reader
-// never sees half a file. Caller holds the lock.
+// never sees half a file. Entries that another process stored in the file
+// since this one read it are kept (on the same key this process's entry
+// wins); a file that no longer parses is replaced. Caller holds the lock.
 void write_locked(TuneCache& c) {
+    std::string text;
+    std::map<std::string, tdct_tune> disk;
+    if (read_file(c.path.c_str(), &text) > 0 && parse(text, disk) == TDCT_OK)
+        for (const auto& kv : disk) c.entries.emplace(kv.first, kv.second);
+    c.stats.entries = (int64_t)c.entries.size();
     std::string out = "{\n \"format\": \"tdct-autotune-1\",\n \"entries\": {";
     bool first = true;
     for (const auto& kv : c.entries) {
@@ -298,14 +314,16 @@ int tdct_tune_cache_open(const char* path) {
 }
 
 int tdct_tune_cache_info(tdct_tune_cache_stats* out) {
-    if (!out) return TDCT_EINVAL;
-    tdct::TuneCache& c = tdct::cache();
-    std::lock_guard<std::mutex> lk(c.mu);
-    tdct::ensure_env_locked(c);
-    *out = c.stats;
-    out->on = c.on ? 1 : 0;
-    out->entries = (int64_t)c.entries.size();
-    return TDCT_OK;
+    return tdct::abi_call([&]() -> int {
+        if (!out) return TDCT_EINVAL;
+        tdct::TuneCache& c = tdct::cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        tdct::ensure_env_locked(c);  // may read the file $TDCT_TUNE_CACHE names
+        *out = c.stats;
+        out->on = c.on ? 1 : 0;
+        out->entries = (int64_t)c.entries.size();
+        return TDCT_OK;
+    });
 }
 
 }  // extern "C"

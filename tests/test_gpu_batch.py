@@ -246,7 +246,8 @@ def test_autotune_cache_skips_the_search_and_keeps_the_shape(tdct, tmp_path):
     candidates and stores the winner in the file; a new process (here: the
     file opened again) applies the stored shape to another plan of the same
     class without timing anything, and that plan's outputs are the oracle's.
-    A plan of another class misses."""
+    A plan of another class misses; its store keeps an entry another process
+    wrote to the file in the meantime."""
     import time
     path = str(tmp_path / "tune.json")
     try:
@@ -275,6 +276,13 @@ def test_autotune_cache_skips_the_search_and_keeps_the_shape(tdct, tmp_path):
             tdct.tdct_plan_free(pb)
         info = tdct.tdct_tune_cache_info()
         assert info["hits"] == 1 and info["stores"] == 0
+        # another process stores a class in the file meanwhile: kept by the
+        # next rewrite
+        import json
+        doc = json.load(open(path))
+        other = "gfx950/src=00000000ffffffff/ops=4/tiles=3/aligned=0"
+        doc["entries"][other] = [1, 4096, 1, 0, 0]
+        json.dump(doc, open(path, "w"))
         C = Ragged(tdct, seed=22, big=True)  # more tiles: another size class
         pc = tdct.tdct_batch_plan(C.descs, C.qtabs)
         try:
@@ -284,7 +292,9 @@ def test_autotune_cache_skips_the_search_and_keeps_the_shape(tdct, tmp_path):
         finally:
             tdct.tdct_plan_free(pc)
         info = tdct.tdct_tune_cache_info()
-        assert info["stores"] == 1 and info["entries"] == 2 and info["write_errors"] == 0
+        assert info["stores"] == 1 and info["entries"] == 3 and info["write_errors"] == 0
+        assert json.load(open(path))["entries"][other] == [1, 4096, 1, 0, 0]
+        assert len(json.load(open(path))["entries"]) == 3
     finally:
         tdct.tdct_tune_cache_open(None)
 
