@@ -253,8 +253,8 @@ void tdct_plan_free(tdct_plan* plan);
 int tdct_run_per_image(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
                        int32_t nq, void* stream);
 
-/* For callers that cannot allocate device memory (code under stream
- * capture, tight serving loops, harnesses that forbid hipMalloc): the work
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the work
  * of tdct_batch_plan + tdct_batch_run in one call, with no plan object and
  * no allocation. The tables go into a fixed device array of
  * TDCT_STATIC_TABLE_BYTES (16 MiB) that the library holds on each GPU it
@@ -267,7 +267,10 @@ int tdct_run_per_image(const tdct_image_desc* imgs, int32_t n, const tdct_qtable
  * performs synchronously with respect to the host; then the kernel is queued
  * on `stream`. Every call on one GPU shares that GPU's array: calls on one
  * stream are ordered, but calls that overlap on one GPU (other streams, other
- * threads) race and must be serialised by the caller. */
+ * threads) race and must be serialised by the caller. Not for stream
+ * capture: the table copy reads the library's static host buffer, which the
+ * next call overwrites, so a captured graph could replay another call's
+ * tables. */
 #define TDCT_STATIC_TABLE_BYTES (16 << 20)
 int tdct_batch_run_static(const tdct_image_desc* imgs, int32_t n, const tdct_qtable* qtabs,
                           int32_t nq, const tdct_tune* tune_or_null, void* stream);

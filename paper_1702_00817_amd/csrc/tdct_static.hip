@@ -18,6 +18,8 @@
 // overlap on one GPU (other streams, other threads) race: a later copy can
 // overwrite tables an earlier kernel still reads. Nothing in the array has
 // to start at zero: every byte a kernel reads is written by its own call.
+// The call is not for stream capture: its copy reads g_stage, which the
+// next call rewrites.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
