@@ -29,11 +29,14 @@ and, unless --no-extras:
   video         256 4:2:0 frames to int8 zigzag, one graph vs one launch per plane;
   batched       10,000 ragged images as one persistent launch replayed from a
                 hipGraph vs one plain launch per image;
-  serving       Poisson request streams (60 s per rate) served with continuous
-                batching and with a plain launch per request, and (shorter) by
-                the resident kernel and with host payloads over PCIe:
-                p50/p99/p99.9 latency, the tail's make-up, Gpixel/s;
-  quality       (--quality) the zonal-coding sweep against the exact DCT.
+  serving       Poisson request streams (60 s per rate) served by the resident
+                kernel and with a plain launch per request, and (shorter) with
+                continuous batching into launched kernels and with host payloads
+                over PCIe: p50/p99/p99.9 latency, the tail's make-up, Gpixel/s,
+                and the capacity of each form under a burst;
+  quality       the zonal-coding sweep against the exact DCT (--no-quality
+                skips it).
+config.leg_seconds gives the wall time of each part of the run.
 cpu_baseline also holds the oracle beside the 512 x 512 latency leg, the
 ragged batch and the video frames, and its check of the served outputs (a
 seeded 1 % of each trace plus every request of 32 Mpx or more).
@@ -631,9 +634,9 @@ def quality_leg(tdct, torch, stream, n_images=45, side=512, rs=range(2, 46)):
     sse_dct = np.zeros((n_images, len(rs)))
     for i, img in enumerate(imgs):
         X = img.reshape(side // 8, 8, side // 8, 8).transpose(0, 2, 1, 3).astype(np.float64) - 128
-        Y = np.einsum("ab,xybc,dc->xyad", C, X, C)
+        Y = C @ X @ C.T  # per block: C X C^t
         for k, r in enumerate(rs):
-            Z = np.einsum("ba,xybc,cd->xyad", C, Y * (rank < r), C)
+            Z = C.T @ (Y * (rank < r)) @ C
             rec = np.clip(np.floor(Z + 0.5) + 128, 0, 255)
             sse_dct[i, k] = ((rec - X - 128) ** 2).sum()
     npx = side * side
@@ -1264,8 +1267,8 @@ def main():
                          "capacity is measured apart)")
     ap.add_argument("--serving-aux-seconds", type=float, default=4.0,
                     help="trace length per rate for host payloads and the burst")
-    ap.add_argument("--quality", action="store_true",
-                    help="also run the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--legs", default="",
                     help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--fused-tune", default="",
@@ -1512,7 +1515,7 @@ def main():
         cpu("serving", cpu_baseline_serving, tdct, torch, sctx, (200, 1000, 5000))
         del sctx
         torch.cuda.empty_cache()
-    if args.quality:
+    if want("quality") and not args.no_quality:
         mark("quality")
         log("quality leg...")
         result["quality"] = quality_leg(tdct, torch, stream)
