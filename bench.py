@@ -54,6 +54,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# The workloads by number (the 64 x 4096^2 step always runs): the extra legs
+# each one adds.
+CONFIG_LEGS = {1: "latency_512", 2: "", 3: "batched", 4: "video", 5: "serving"}
 MAX_BATCH_PX = 64 << 20  # serving: a launch stops growing at 64 Mpx (~35 us of HBM time)
 
 
@@ -1271,6 +1274,10 @@ def main():
                     help="skip the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--legs", default="",
                     help="comma-separated subset of the extra legs to run (default: all)")
+    ap.add_argument("--config", type=int, choices=sorted(CONFIG_LEGS), default=None,
+                    help="one workload beside the headline step: 1 the 512 x 512 latencies, 2 the "
+                         "64 x 4096^2 step alone, 3 the 10,000 ragged images, 4 the 4:2:0 video "
+                         "frames, 5 the serving streams")
     ap.add_argument("--fused-tune", default="",
                     help="fixed launch shape 'WPG,GPC,TW[,XCD[,PC]]' for the fused round trip")
     ap.add_argument("--tune-cache", default=None,
@@ -1287,6 +1294,11 @@ def main():
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.config is not None:
+        if args.legs or args.no_extras:
+            ap.error("--config names the legs itself (no --legs or --no-extras with it)")
+        args.legs = CONFIG_LEGS[args.config]
+        args.no_extras = not args.legs
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the codec shards by image (or block range) with "
