@@ -315,11 +315,12 @@ def graph_replay_ms(tdct, torch, plan, stream, warm=5, n=11):
     return sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(n))[n // 2]
 
 
-def batched_leg(tdct, torch, stream, n=10000, reps=5):
+def batched_leg(tdct, torch, stream, n=10000, reps=5, per_image=True):
     """10,000 ragged images, encode + decode round trip with coefficients:
     persistent launch (graph replay median) vs one plain launch per image, and vs
     the same per-image launches captured in one hipGraph (no launch
-    overhead: what remains is the cost of 10,000 small grids)."""
+    overhead: what remains is the cost of 10,000 small grids). per_image=False
+    leaves the per-image comparisons out (for runs under a profiler)."""
     import numpy as np
 
     import synth
@@ -341,44 +342,51 @@ def batched_leg(tdct, torch, stream, n=10000, reps=5):
     try:
         tune = tdct.tdct_autotune(plan, stream, reps=2)
         graph_s = graph_replay_ms(tdct, torch, plan, stream) / 1e3
-        tdct.tdct_run_per_image(descs, qs, stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            tdct.tdct_run_per_image(descs, qs, stream)
-        torch.cuda.synchronize()
-        per_s = (time.perf_counter() - t0) / reps
         info = tdct.tdct_plan_info_get(plan)
-        # the per-image launches captured once and replayed
-        want = dst.clone()
-        dst.zero_()
-        torch.cuda.synchronize()
-        cap = torch.cuda.Stream()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=cap):
-            tdct.tdct_run_per_image(descs, qs, cap)
-        g.replay()
-        torch.cuda.synchronize()
-        graph_same = bool(torch.equal(dst, want))
-        del want
-        t0 = time.perf_counter()
-        for _ in range(reps):
+        per_s = per_graph_s = graph_same = None
+        if per_image:
+            tdct.tdct_run_per_image(descs, qs, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                tdct.tdct_run_per_image(descs, qs, stream)
+            torch.cuda.synchronize()
+            per_s = (time.perf_counter() - t0) / reps
+            # the per-image launches captured once and replayed
+            want = dst.clone()
+            dst.zero_()
+            torch.cuda.synchronize()
+            cap = torch.cuda.Stream()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                tdct.tdct_run_per_image(descs, qs, cap)
             g.replay()
-        torch.cuda.synchronize()
-        per_graph_s = (time.perf_counter() - t0) / reps
-        del g
+            torch.cuda.synchronize()
+            graph_same = bool(torch.equal(dst, want))
+            del want
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                g.replay()
+            torch.cuda.synchronize()
+            per_graph_s = (time.perf_counter() - t0) / reps
+            del g
     finally:
         tdct.tdct_plan_free(plan)
     del src, coef, dst
     gbs = 4 * px / graph_s / 1e9
-    return (buf, off, strides, sizes, qs), {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(gbs / 8000.0, 4)},
-            "graph_gpx_s": round(px / graph_s / 1e9, 2), "graph_ms": round(graph_s * 1e3, 3),
-            "per_image_gpx_s": round(px / per_s / 1e9, 2), "per_image_ms": round(per_s * 1e3, 3),
-            "per_image_graph_gpx_s": round(px / per_graph_s / 1e9, 2),
-            "per_image_graph_ms": round(per_graph_s * 1e3, 3), "per_image_graph_same": graph_same,
-            "speedup": round(per_s / graph_s, 2), "bytes_per_px": 4}
+    traffic = load_traffic("roundtrip_ragged_10000")
+    out = {"images": n, "pixels": px, "tiles": info["tiles"], "tune": tune,
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(gbs / 8000.0, 4),
+                        "traffic": traffic["hbm_bytes_per_launch"] if traffic else None},
+           "graph_gpx_s": round(px / graph_s / 1e9, 2), "graph_ms": round(graph_s * 1e3, 3),
+           "bytes_per_px": 4}
+    if per_image:
+        out.update({"per_image_gpx_s": round(px / per_s / 1e9, 2), "per_image_ms": round(per_s * 1e3, 3),
+                    "per_image_graph_gpx_s": round(px / per_graph_s / 1e9, 2),
+                    "per_image_graph_ms": round(per_graph_s * 1e3, 3), "per_image_graph_same": graph_same,
+                    "speedup": round(per_s / graph_s, 2)})
+    return (buf, off, strides, sizes, qs), out
 
 
 PROBES = (("copy", 32), ("read", 16), ("write", 16), ("read1_write2", 48), ("read2_write1", 48),
@@ -573,8 +581,10 @@ def video_leg(tdct, torch, stream, frames=256, reps=5):
     del src, out
     ctx = (host, v, frames)
     gbs = 2 * n / graph_s / 1e9
+    traffic = load_traffic("video_420x256")
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(gbs / 8000.0, 4)}
+            "frac": round(gbs / 8000.0, 4),
+            "traffic": traffic["hbm_bytes_per_launch"] if traffic else None}
     valu = load_valu("video_420x256")
     if valu:
         lane_ops = valu["valu_insts_per_launch"] * 64
@@ -1270,6 +1280,9 @@ def main():
                          "capacity is measured apart)")
     ap.add_argument("--serving-aux-seconds", type=float, default=4.0,
                     help="trace length per rate for host payloads and the burst")
+    ap.add_argument("--no-per-image", action="store_true",
+                    help="leave out the ragged batch's per-image comparisons (120,000 plain "
+                         "launches; for runs under a profiler)")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the zonal-coding quality sweep (PSNR and MSE APE vs the DCT)")
     ap.add_argument("--legs", default="",
@@ -1511,7 +1524,7 @@ def main():
     if want("batched"):
         mark("batched")
         log("batched leg...")
-        bctx, result["batched"] = batched_leg(tdct, torch, stream)
+        bctx, result["batched"] = batched_leg(tdct, torch, stream, per_image=not args.no_per_image)
         roof = result["batched"]["roofline"]
         roof["stream_ceiling"] = {"mix": "read1_write3", "gbs": ceil["read1_write3"],
                                   "frac": round(roof["achieved"] / ceil["read1_write3"], 4)}
