@@ -31,3 +31,18 @@ def test_launch_shape_parsing():
         except SystemExit:
             continue
         raise AssertionError(bad)
+
+
+def test_config_numbers_name_known_legs():
+    """--config N runs the headline step and workload N's leg (2: the step
+    alone); other numbers, or --config with --legs, are refused before any
+    GPU work."""
+    import subprocess
+    import sys
+    assert sorted(bench.CONFIG_LEGS) == [1, 2, 3, 4, 5]
+    assert bench.CONFIG_LEGS[2] == ""
+    for legs in bench.CONFIG_LEGS.values():
+        assert legs in ("", "latency_512", "batched", "video", "serving")
+    for args in (["--config", "6"], ["--config", "3", "--legs", "video"], ["--config", "1", "--no-extras"]):
+        r = subprocess.run([sys.executable, bench.__file__] + args, capture_output=True, text=True, timeout=60)
+        assert r.returncode == 2 and "--config" in r.stderr
