@@ -330,7 +330,13 @@ typedef struct {
     int32_t tune_cache;       /* 1: each batch launch takes the autotune cache's shape for
                                  its class (nearest size class within a factor of 4), when
                                  the cache holds one; otherwise `tune` */
-    int32_t reserved2;
+    int32_t idle_poll_us;     /* the scheduler polls (completions, arrivals) this long after the
+                                 last activity before it sleeps until the next submit (0: 2000;
+                                 at most 10^7). A request submitted to a sleeping scheduler is
+                                 launched by the submitting thread at once, but its completion
+                                 is seen only once the scheduler's thread has woken: polling
+                                 longer spends a host core to keep that wake-up out of the
+                                 latency at low request rates */
 } tdct_server_cfg;
 
 typedef struct {

@@ -77,7 +77,7 @@ class tdct_server_cfg(ctypes.Structure):
                 ("resident", ctypes.c_int32), ("resident_workers", ctypes.c_int32),
                 ("resident_idle_us", ctypes.c_int32), ("resident_jobs", ctypes.c_int32),
                 ("resident_tiles", ctypes.c_int32), ("resident_reserved", ctypes.c_int32),
-                ("tune_cache", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("tune_cache", ctypes.c_int32), ("idle_poll_us", ctypes.c_int32)]
 
 
 class tdct_tune_cache_stats(ctypes.Structure):
@@ -358,7 +358,8 @@ def tdct_batch_run_static(descs, qtabs, tune=None, stream=None):
 
 def server_cfg(budget_bytes, streams=4, max_batch=64, max_wait_us=0, batching=1, tune=None,
                fake_device_us=0, fake_fail_every=0, max_batch_px=0, resident=0, resident_workers=0,
-               resident_idle_us=0, resident_jobs=0, resident_tiles=0, tune_cache=0) -> tdct_server_cfg:
+               resident_idle_us=0, resident_jobs=0, resident_tiles=0, tune_cache=0,
+               idle_poll_us=0) -> tdct_server_cfg:
     c = tdct_server_cfg()
     c.budget_bytes, c.streams, c.max_batch = budget_bytes, streams, max_batch
     c.max_wait_us, c.batching, c.max_batch_px = max_wait_us, batching, max_batch_px
@@ -367,7 +368,7 @@ def server_cfg(budget_bytes, streams=4, max_batch=64, max_wait_us=0, batching=1,
     c.fake_device_us, c.fake_fail_every = fake_device_us, fake_fail_every
     c.resident, c.resident_workers, c.resident_idle_us = resident, resident_workers, resident_idle_us
     c.resident_jobs, c.resident_tiles = resident_jobs, resident_tiles
-    c.tune_cache = tune_cache
+    c.tune_cache, c.idle_poll_us = tune_cache, idle_poll_us
     return c
 
 

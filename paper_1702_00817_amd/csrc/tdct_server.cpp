@@ -168,6 +168,7 @@ struct tdct_server {
     bool fake = false;
     int num_cus = 0;
     std::string arch;  // device architecture (autotune cache keys)
+    double poll_us = 0;  // the scheduler polls this long after the last activity
     Arena* arena = nullptr;
     char* arena_base = nullptr;
     std::mutex mu;
@@ -571,8 +572,10 @@ double launch_step(tdct_server* s, std::unique_lock<std::mutex>& lk, double now,
 }
 
 // How long the scheduler keeps polling after the last activity before it
-// sleeps on its condition variable.
+// sleeps on its condition variable, unless the configuration says otherwise
+// (idle_poll_us).
 constexpr double kSpinUs = 2000.0;
+constexpr int32_t kMaxIdlePollUs = 10000000;
 
 // ---- resident mode -------------------------------------------------------
 
@@ -970,8 +973,8 @@ void scheduler(tdct_server* s) {
         bool busy_now = s->cfg.resident && !s->res.live.empty();
         for (Slot& sl : s->slots) busy_now |= sl.busy;
         const double tnow = s->now_us();
-        if (busy_now || tnow - s->last_activity_us < kSpinUs) {
-            if (next_deadline < 0 || busy_now || next_deadline - tnow < kSpinUs) {
+        if (busy_now || tnow - s->last_activity_us < s->poll_us) {
+            if (next_deadline < 0 || busy_now || next_deadline - tnow < s->poll_us) {
                 lk.unlock();
                 std::this_thread::yield();
                 lk.lock();
@@ -1000,7 +1003,8 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
         if (!cfg || !out) return TDCT_EINVAL;
         *out = nullptr;
         if (cfg->budget_bytes <= 0 || cfg->streams < 1 || cfg->streams > 16 || cfg->max_batch < 0 ||
-            cfg->max_wait_us < 0 || cfg->max_batch_px < 0)
+            cfg->max_wait_us < 0 || cfg->max_batch_px < 0 || cfg->idle_poll_us < 0 ||
+            cfg->idle_poll_us > kMaxIdlePollUs)
             return TDCT_EINVAL;
         // On any early return the partly built server goes through
         // tdct_server_destroy, which frees whatever it holds.
@@ -1009,6 +1013,7 @@ int tdct_server_create(const tdct_server_cfg* cfg, tdct_server** out) {
         if (!s) return TDCT_ENOMEM;
         s->cfg = *cfg;
         if (s->cfg.max_batch == 0) s->cfg.max_batch = 256;
+        s->poll_us = cfg->idle_poll_us > 0 ? (double)cfg->idle_poll_us : kSpinUs;
         // Zero fields take the batch form's default shape (one wave per
         // workgroup and one tile per wave, so a small batch's waves land on
         // as many CUs as there are); out-of-range fields are rejected.

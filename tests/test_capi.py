@@ -219,6 +219,26 @@ def test_fake_server_launches_lone_requests_from_submit(tdct):
         tdct.tdct_server_destroy(s)
 
 
+def test_fake_server_idle_poll_window(tdct):
+    """idle_poll_us sets how long the scheduler polls after the last activity
+    (0: 2 ms); out-of-range values are refused at create. With a window longer
+    than the gaps between requests, spaced requests complete as before."""
+    for bad in (-1, 10000001):
+        with pytest.raises(tdct.TdctError) as e:
+            tdct.tdct_server_create(tdct.server_cfg(1 << 24, fake_device_us=100, idle_poll_us=bad))
+        assert e.value.status == tdct.TDCT_EINVAL
+    s = tdct.tdct_server_create(tdct.server_cfg(1 << 24, streams=2, fake_device_us=200, idle_poll_us=50000))
+    try:
+        for k in range(5):
+            time.sleep(0.006)
+            t = tdct.tdct_server_submit(s, _req(tdct, k % 2, 64, 32))
+            r = tdct.tdct_server_wait(s, t)
+            assert r.status == tdct.TDCT_OK and r.batch_size == 1
+        assert tdct.tdct_server_stats(s)["completed"] == 5
+    finally:
+        tdct.tdct_server_destroy(s)
+
+
 def test_fake_server_admission_never_exceeds_budget(tdct):
     budget = 3 * 64 * 64 * 2  # room for three encode outputs of 64 x 64
     s = tdct.tdct_server_create(tdct.server_cfg(budget, streams=4, max_batch=8, fake_device_us=300))
