@@ -17,7 +17,7 @@ namespace tdct {
 // One image, quantiser constants in the kernel arguments. Wave w handles
 // tiles w, w + nwaves, ... of the image, each of `tb` blocks (at most the
 // op's tile size).
-template <int OP>
+template <int OP, int PC>
 __global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QConst qc,
                                                     uint32_t ntiles, uint32_t tb) {
     extern __shared__ v4u lds[];
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void plain_kernel(const ImgDesc d, const QCons
     for (uint32_t t = wave; t < ntiles; t += nwaves) {
         const uint32_t first = t * tb;
         const uint32_t count = min(tb, nblk - first);
-        run_tile<OP>(d, qc, first, count, lane, wl);
+        run_tile<OP, PC>(d, qc, first, count, lane, wl);
     }
 }
 
@@ -203,13 +203,25 @@ static uint32_t device_simds() {
 // tile (two blocks per lane) shrinks to 64 blocks while 128-block tiles
 // would leave SIMDs without a wave: each wave then does half the serial
 // work (one block per lane) and there are twice as many of them.
+// Pixel accesses of a plain call: cached for planes up to kPlainCachedPx
+// pixels, streaming above. Measured with back-to-back calls over rotating
+// sources: below about 4 Mpx cached accesses took the encoder and decoder
+// 3-9 % faster (1000x1000 and 2040x1528; such planes sit in the 256 MB MALL
+// between producer and consumer, and rows that end inside a 128-byte line
+// meet their neighbour tile's part in L2), while from 4096x4096 up they were
+// as fast for the encoder and 5-8 % slower for the decoder.
+constexpr int64_t kPlainCachedPx = 4 << 20;
+
 template <int OP>
 static int launch_plain(const ImgDesc& d, const QConst& qc, hipStream_t stream) {
     uint32_t tb = (uint32_t)tile_blocks(OP);
     if (tb > 64 && (uint64_t)(d.nblk + tb - 1) / tb < device_simds()) tb = 64;
     const uint32_t ntiles = (uint32_t)((d.nblk + tb - 1) / tb);
     const uint32_t lds = lds_wave_bytes(1 << OP);
-    hipLaunchKernelGGL(plain_kernel<OP>, dim3(ntiles), dim3(64), lds, stream, d, qc, ntiles, tb);
+    if (d.nblk * 64 <= kPlainCachedPx)
+        hipLaunchKernelGGL((plain_kernel<OP, PX_CACHED>), dim3(ntiles), dim3(64), lds, stream, d, qc, ntiles, tb);
+    else
+        hipLaunchKernelGGL((plain_kernel<OP, PX_STREAM>), dim3(ntiles), dim3(64), lds, stream, d, qc, ntiles, tb);
     return check_launch("plain kernel launch");
 }
 
