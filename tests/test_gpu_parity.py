@@ -128,6 +128,31 @@ def test_roundtrip_kernel(tdct):
             assert np.array_equal(qo.host().view(np.int16).reshape(nblk, 64), q_ref)
 
 
+@pytest.mark.parametrize("w,h", [(2048, 2048), (2056, 2048)])
+def test_plain_calls_on_both_sides_of_the_pixel_policy_size(tdct, w, h):
+    """Plain calls take cached pixel accesses up to 4 Mpx and streaming ones
+    above: 2048 x 2048 is exactly 4 Mpx, 2056 x 2048 just above. Encode, decode
+    and the fused round trip (with coefficients) on a plane whose row stride is
+    not a multiple of 128 bytes, every output against the oracle."""
+    stride = w + 48
+    img = synth.textured(w, h, w + h, stride=stride)
+    Q = synth.qtable(1, 4)
+    got = _encode(tdct, img, Q, w=w)
+    ref = O.quantise(img, Q, 64, w=w)
+    assert np.array_equal(got, ref)
+    rec = _decode(tdct, ref, Q, w, h, dst_stride=stride)
+    assert np.array_equal(rec, O.inverse(ref, Q, w, h))
+    _, sp = plane_dev(img)
+    nblk = (w // 8) * (h // 8)
+    qo, out = Guarded(nblk * 128), Guarded(h * stride)
+    tdct.tdct_roundtrip(sp, stride, w, h, Q, 10, qo.ptr, out.ptr, stride)
+    sync()
+    q_rt, rec_rt = O.roundtrip(img, Q, 10, w=w)
+    assert qo.guards_intact() and out.guards_intact()
+    assert np.array_equal(qo.host().view(np.int16).reshape(nblk, 64), q_rt)
+    assert np.array_equal(out.host().reshape(h, stride)[:, :w], rec_rt)
+
+
 def test_roundtrip_in_place(tdct):
     w, h = 64, 32
     img = synth.textured(w, h, 8)
