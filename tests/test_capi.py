@@ -258,8 +258,10 @@ def test_fake_server_admission_never_exceeds_budget(tdct):
                     tdct.tdct_server_release(s, t)
             assert tdct.tdct_server_stats(s)["arena_high_water"] <= budget
             time.sleep(0.0005)
-        # FIFO: completion order follows submission order in groups of three
-        assert done[:3] == sorted(done[:3]) and max(done[:3]) < min(done[3:])
+        # FIFO: the first three requests fit and run (in parallel, on three
+        # stream slots, so their order among themselves is open); every later
+        # one waits for a release
+        assert sorted(done[:3]) == tickets[:3] and max(done[:3]) < min(done[3:])
         st = tdct.tdct_server_stats(s)
         assert st["arena_high_water"] <= budget and st["rejected"] == 1
     finally:
