@@ -49,16 +49,23 @@ __device__ __forceinline__ void st_nt2(void* p, v2u v) {
 }
 
 // Output stores that write through L2 to memory (agent-scope coherent, sc1)
-// and carry the streaming hint. Each XCD has its own L2, so ordinary stores
-// of one wave become visible to other XCDs and to copy engines only once that
-// L2 is written back; a wave that stores this way makes its outputs visible
-// device-wide as soon as its stores complete (s_waitcnt vmcnt(0)), without
-// writing back the whole L2 of its XCD.
-constexpr int kBufSc1Nt = 16 | 2;              // cache-policy bits: sc1, nt
+// and carry the streaming hint (nt). Each XCD has its own L2, so ordinary
+// stores of one wave become visible to other XCDs and to copy engines only
+// once that L2 is written back; a wave that stores this way makes its outputs
+// visible device-wide as soon as its stores complete (s_waitcnt vmcnt(0)),
+// without writing back the whole L2 of its XCD.
+constexpr int kBufSc1 = 16;                    // cache-policy bits: sc1
+constexpr int kBufSc1Nt = kBufSc1 | 2;         // sc1, nt
 constexpr uint32_t kBufRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
+// An 8-byte pixel-row store at any address (a buffer store would need a
+// wave-uniform base within 4 GiB of every lane's row). No builtin gives a
+// global store both sc1 and nt, so the instruction is written out; it takes
+// no output register, and the count-off's s_waitcnt vmcnt(0) covers it like
+// any other store. (Measured on a burst of decode requests: 1607-1728 Gpx/s
+// with sc1 nt pixel stores and sc1 coefficient loads, 1210-1256 with sc1
+// stores and sc1 nt loads.)
 __device__ __forceinline__ void st_wt2(void* p, v2u v) {
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("global_store_dwordx2 %0, %1, off sc1 nt" ::"v"(p), "v"(v) : "memory");
 }
 __device__ __forceinline__ void st_wt1(uint8_t* p, uint8_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -66,7 +73,9 @@ __device__ __forceinline__ void st_wt1(uint8_t* p, uint8_t v) {
 // Loads that never return a stale L2 line (sc1): what another agent (a copy
 // engine, a kernel on another XCD) wrote to memory before the load is seen.
 // A kernel that keeps running while its inputs change between requests reads
-// them this way instead of invalidating its XCD's whole L2.
+// them this way instead of invalidating its XCD's whole L2. They carry no
+// streaming hint: with it, both the pixel-row loads and the coefficient-run
+// loads ran slower in the resident kernel.
 __device__ __forceinline__ v2u ld_wt2(const void* p) {
     return __builtin_bit_cast(v2u, __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT));
@@ -79,7 +88,7 @@ __device__ __forceinline__ uint32_t ld_wt1(const uint8_t* p) {
 __device__ __forceinline__ v4u ld_wt4(const void* base, uint32_t off, uint32_t limit) {
     const __amdgpu_buffer_rsrc_t r =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)limit, (int)kBufRsrcWord3);
-    return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, kBufSc1Nt));
+    return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, kBufSc1));
 }
 
 // 16-byte store at base + off (base wave-uniform, off per lane, both in
