@@ -187,12 +187,16 @@ void write_locked(TuneCache& c) {
     std::string out = "{\n \"format\": \"tdct-autotune-1\",\n \"entries\": {";
     bool first = true;
     for (const auto& kv : c.entries) {
-        char line[512];
+        // keys hold no quote, backslash or newline (the parser refuses them),
+        // so they go out as they are, whatever their length
+        char nums[96];
         const tdct_tune& t = kv.second;
-        snprintf(line, sizeof line, "%s\n  \"%s\": [%d, %d, %d, %d, %d]", first ? "" : ",",
-                 kv.first.c_str(), t.waves_per_group, t.groups_per_cu, t.tile_waves, t.xcd_remap,
-                 t.pixel_cache);
-        out += line;
+        snprintf(nums, sizeof nums, "[%d, %d, %d, %d, %d]", t.waves_per_group, t.groups_per_cu,
+                 t.tile_waves, t.xcd_remap, t.pixel_cache);
+        out += first ? "\n  \"" : ",\n  \"";
+        out += kv.first;
+        out += "\": ";
+        out += nums;
         first = false;
     }
     out += "\n }\n}\n";

@@ -13,10 +13,20 @@
 #include <cstdio>
 #include <cstring>
 #include <random>
+#include <string>
 #include <thread>
 #include <vector>
 
+#include <unistd.h>
+
 #include "tdct.h"
+
+namespace tdct {
+// Stores one autotune result under `key` and rewrites the cache file (the
+// library's own entry point for its autotuner, declared here to drive the
+// file code without a device).
+void tune_cache_put(const std::string& key, const tdct_tune& t);
+}
 
 static std::atomic<int> g_failures{0};
 
@@ -294,6 +304,32 @@ static void argument_checks() {
     for (int st = 0; st > -8; --st) CHECK(std::strcmp(tdct_strerror(st), "unknown status") != 0);
 }
 
+// The autotune cache file: a key far longer than any the library makes
+// survives a rewrite, and entries another process wrote to the file since it
+// was opened are merged in.
+static void tune_cache_file() {
+    const std::string path = "/tmp/tdct_tune_cache_driver_" + std::to_string((long)getpid()) + ".json";
+    const std::string longkey(3000, 'k');
+    auto write = [&](const std::string& entries) {
+        FILE* f = std::fopen(path.c_str(), "wb");
+        CHECK(f != nullptr);
+        if (!f) return;
+        std::fprintf(f, "{\n \"format\": \"tdct-autotune-1\",\n \"entries\": {%s\n }\n}\n", entries.c_str());
+        std::fclose(f);
+    };
+    write("\n  \"" + longkey + "\": [4, 1, 2, 1, 0]");
+    CHECK(tdct_tune_cache_open(path.c_str()) == TDCT_OK);
+    tdct::tune_cache_put("driver-a", tdct_tune{2, 4096, 1, 0, 1});
+    write("\n  \"" + longkey + "\": [4, 1, 2, 1, 0],\n  \"driver-other\": [1, 16, 1, 1, 1]");
+    tdct::tune_cache_put("driver-b", tdct_tune{8, 1, 1, 1, 1});
+    tdct_tune_cache_stats st;
+    CHECK(tdct_tune_cache_info(&st) == TDCT_OK && st.entries == 4 && st.write_errors == 0);
+    CHECK(tdct_tune_cache_open(path.c_str()) == TDCT_OK);  // the rewritten file parses
+    CHECK(tdct_tune_cache_info(&st) == TDCT_OK && st.on == 1 && st.entries == 4);
+    CHECK(tdct_tune_cache_open(nullptr) == TDCT_OK);
+    std::remove(path.c_str());
+}
+
 #define RUN(call)                                              \
     do {                                                       \
         std::fprintf(stderr, "scenario: %s\n", #call);         \
@@ -310,6 +346,7 @@ int main() {
     RUN(budget_pressure());
     RUN(replay_and_shutdown());
     RUN(resident_mode());
+    RUN(tune_cache_file());
     const int f = g_failures.load();
     std::printf("fake-device driver: %s (%d failed checks)\n", f ? "FAILED" : "ok", f);
     return f ? 1 : 0;
