@@ -365,6 +365,49 @@ def test_resident_large_and_ragged_requests(tdct):
             tdct.tdct_server_destroy(srv)
 
 
+def test_resident_unaligned_encode_inputs(tdct):
+    """Encode requests whose pixel rows are not 8-byte aligned (an odd start
+    address, an odd stride) take the resident kernel's byte-wise coherent
+    loads; every output equals the oracle in full, next to an aligned request
+    served by the same launch."""
+    import torch
+    hip = _hip()
+    side, stride = 1032, 1037
+    img = synth.textured(side, side, 9100)
+    host = np.zeros(side * stride + 64, np.uint8)
+    base = 3
+    for y in range(side):
+        host[base + y * stride: base + y * stride + side] = img[y]
+    dbuf = torch.from_numpy(host).cuda()
+    aligned = torch.from_numpy(img).cuda()
+    # (w, h, byte offset of the window's first pixel inside the plane)
+    cases = [(1032, 1032, 0), (520, 776, 1 + 5 * stride), (8, 8, 7 + stride), (1024, 16, 5)]
+    srv = tdct.tdct_server_create(tdct.server_cfg(1 << 30, resident=1, resident_workers=64,
+                                                  resident_idle_us=5000))
+    try:
+        tickets = []
+        for k, (w, h, off) in enumerate(cases):
+            Q = synth.qtable(1, 1 + k)
+            tickets.append(tdct.tdct_server_submit(srv, tdct.request(
+                tdct.OP_ENCODE, w, h, dbuf.data_ptr() + base + off, Q, keep=48, in_stride=stride)))
+        ta = tdct.tdct_server_submit(srv, tdct.request(tdct.OP_ENCODE, side, side, aligned,
+                                                       synth.qtable(1, 2), keep=48, in_stride=side))
+        for k, (w, h, off) in enumerate(cases):
+            r = tdct.tdct_server_wait(srv, tickets[k])
+            assert r.status == tdct.TDCT_OK
+            got = _read(hip, r.output, r.output_bytes).view(np.int16).reshape(-1, 64)
+            y0, x0 = divmod(off, stride)
+            window = np.ascontiguousarray(img[y0:y0 + h, x0:x0 + w])
+            assert np.array_equal(got, O.quantise(window, synth.qtable(1, 1 + k), 48, threads=8)), (w, h, off)
+        r = tdct.tdct_server_wait(srv, ta)
+        assert r.status == tdct.TDCT_OK
+        got = _read(hip, r.output, r.output_bytes).view(np.int16).reshape(-1, 64)
+        assert np.array_equal(got, O.quantise(img, synth.qtable(1, 2), 48, threads=8))
+        assert tdct.tdct_server_last_error(srv) == ""
+    finally:
+        tdct.tdct_server_destroy(srv)
+
+
 # ---- the serving workload at its own request sizes ---------------------------
 # Sides log-uniform multiples of 8 in [32, 8192] with aspect <= 4, encode and
 # decode with p = 1/2, s in {1..8}, payloads windows of 8192^2 planes; plus
