@@ -31,7 +31,8 @@ and, unless --no-extras:
                 hipGraph vs one plain launch per image;
   serving       Poisson request streams (60 s per rate) served by the resident
                 kernel and with a plain launch per request, and (shorter) with
-                continuous batching into launched kernels and with host payloads
+                continuous batching into launched kernels, with a plain launch
+                per request over that same shorter trace, and with host payloads
                 over PCIe: p50/p99/p99.9 latency, the tail's make-up, Gpixel/s,
                 and the capacity of each form under a burst;
   quality       the zonal-coding sweep against the exact DCT (--no-quality
@@ -787,7 +788,8 @@ def tune_serving_classes(tdct, torch, P, rate=5000, seconds=4.0, sizes=(2, 4, 8,
 
 
 def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), streams=4,
-                resident_workers=0, modes=("resident", "per_request", "batched", "host_io_batched"),
+                resident_workers=0,
+                modes=("resident", "per_request", "batched", "per_request_short", "host_io_batched"),
                 batched_seconds=None):
     """Poisson encode/decode requests (the serving workload: sides log-uniform
     multiples of 8 in [32, 8192], aspect <= 4, s in {1..8}) served by
@@ -795,6 +797,8 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
     per rate, with device-resident payloads: the resident polling kernel
     (the served form) and one plain launch per request for `seconds`,
     continuous batching into launched batch kernels for `batched_seconds`,
+    one plain launch per request again over that same shorter trace
+    (per_request_short: the like-for-like comparison for batching),
     and batching with host payloads copied over PCIe (host_io_batched, the
     PCIe-inclusive rate) for `aux_seconds`. Per mode: latency
     percentiles, the tail's make-up (share of p99-and-above requests served in
@@ -818,14 +822,15 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
     for rate in rates:
         res = {}
         for mode in modes:
-            secs = {"resident": seconds, "per_request": seconds,
-                    "batched": batched_seconds or seconds}.get(mode, aux_seconds)
+            secs = {"resident": seconds, "per_request": seconds, "batched": batched_seconds or seconds,
+                    "per_request_short": batched_seconds or seconds}.get(mode, aux_seconds)
+            cfg_mode = "per_request" if mode == "per_request_short" else mode
             tr = synth.serving_trace(rate, secs, seed=5)
             traces[(rate, secs)] = tr
             px = (tr["w"] * tr["h"]).astype(np.int64)
             ra = serving_requests(tdct, tr, P, host_io=(hp, hc, ho) if mode == "host_io_batched" else None)
             arrival = (tr["t"] * 1e6).tolist()
-            srv = tdct.tdct_server_create(serving_cfg(tdct, mode, streams, resident_workers))
+            srv = tdct.tdct_server_create(serving_cfg(tdct, cfg_mode, streams, resident_workers))
             try:
                 t0 = time.perf_counter()
                 _, lat, st, bs = tdct.tdct_server_replay(srv, ra, arrival, with_batch=True)
@@ -857,7 +862,7 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
             ra = serving_requests(tdct, tr, P)
             px = float((tr["w"] * tr["h"]).sum())
             for mode in modes:
-                if mode == "host_io_batched":
+                if mode in ("host_io_batched", "per_request_short"):
                     continue
                 srv = tdct.tdct_server_create(serving_cfg(tdct, mode, streams, resident_workers))
                 try:
@@ -880,11 +885,23 @@ def serving_leg(tdct, torch, seconds, aux_seconds, rates=(200, 1000, 5000), stre
             a, b = r["resident"], r["per_request"]
             summary["rates"][str(rate)] = {k: a[k] for k in ("p50_us", "p99_us", "p999_us")}
             summary["rates"][str(rate)].update({"per_request_" + k: b[k] for k in ("p50_us", "p99_us", "p999_us")})
+    # continuous batching against one launch per request on the same trace
+    summary["batched_vs_per_request_same_trace"] = {}
+    for rate in rates:
+        r = out[str(rate)]
+        if "batched" in r and "per_request_short" in r:
+            a, b = r["batched"], r["per_request_short"]
+            d = {k: a[k] for k in ("p50_us", "p99_us", "p999_us")}
+            d.update({"per_request_" + k: b[k] for k in ("p50_us", "p99_us", "p999_us")})
+            d["seconds"] = a["seconds"]
+            summary["batched_vs_per_request_same_trace"][str(rate)] = d
     burst = out[str(max(rates))]
     summary["burst_gpx_s"] = {m: burst["burst_" + m]["gpx_s"] for m in modes if "burst_" + m in burst}
     result = {"summary": summary,
               "seconds_per_rate": {"resident": seconds, "per_request": seconds,
-                                   "batched": batched_seconds or seconds, "host_io_batched": aux_seconds},
+                                   "batched": batched_seconds or seconds,
+                                   "per_request_short": batched_seconds or seconds,
+                                   "host_io_batched": aux_seconds},
               "batch_tune_classes": tuned,
               "streams": streams, "budget_gb": 64,
               "resident_workers": resident_workers or "four per CU", "rates": out}
